@@ -1,0 +1,169 @@
+/*
+ * fof.h - periodic Friends-of-Friends group labelling on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Operation (paper, Section 1 footnote): the groups are the connected
+ * components of the graph whose edges join every pair of particles at most
+ * l_x apart. Distances are periodic minimum-image distances in a cubic box of
+ * side L. Each group is labelled with its smallest particle index, the label a
+ * union-by-root forest produces when the larger root always points to the
+ * smaller one and roots start at the particle's own offset (Section 2,
+ * Section 3.1). Group sizes are counted at the root (Section 3.4.1).
+ *
+ * Link predicate (fixed here because the paper does not print it): for FP32
+ * coordinates promoted exactly to double, per axis t = a - b, then t -= L if
+ * t > L/2 and t += L if t < -L/2; r2 = (tx*tx + ty*ty) + tz*tz, every
+ * operation rounded to nearest in double with no fused multiply-add; the pair
+ * is linked iff r2 <= l_x*l_x (or r2 < l_x*l_x with fof_options.strict_less).
+ * FOF_PRED_FP32_FILTER decides almost every pair in FP32 and re-decides in
+ * double only the pairs inside a proven rounding band around l_x^2, so both
+ * predicates give exactly the same groups.
+ *
+ * Pipeline: fof_build_cells (bin particles into cells of side >= l_x with a
+ * counting sort), fof_link (cell-pair link search plus lock-free union-find:
+ * find with path halving, a compare-and-swap that hooks the larger root under
+ * the smaller, Section 3.2), fof_finalize (flatten the forest, relabel to the
+ * smallest original index, count group sizes).
+ *
+ * Conventions
+ *  - All device pointers are HIP device memory on the context's device. The
+ *    caller owns the positions, the outputs and the workspace; the library
+ *    owns only the context and a small pinned staging buffer.
+ *  - build/link/finalize enqueue work on the context's stream and return
+ *    without waiting, except where a host output pointer is given.
+ *  - build/link/finalize allocate no device memory.
+ *  - Host-detectable errors return before any device work is enqueued. A
+ *    coordinate that is not finite or lies outside [0, L) is detected on the
+ *    device, latched, and returned by the next synchronising call
+ *    (fof_finalize with a non-NULL h_n_groups, fof_read_n_groups,
+ *    fof_get_stats); the outputs of that run are then undefined.
+ *  - No C++ exception crosses this interface.
+ *  - Boxes: n_boxes >= 1 independent periodic boxes are processed together.
+ *    Box k holds particles h_box_offsets[k] .. h_box_offsets[k+1]-1 of the
+ *    position array, with side h_box[k] and linking length h_lx[k]. Labels
+ *    are box-local indices. n_boxes = 1 is the plain single-box problem.
+ */
+#ifndef FOF_H
+#define FOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fof_ctx fof_ctx;
+
+typedef enum {
+    FOF_OK = 0,
+    FOF_ERR_INVALID_ARG = 1,   /* null pointer, bad count, bad box or linking length */
+    FOF_ERR_OUT_OF_BOX = 2,    /* a coordinate not finite or outside [0, L) (latched on the device) */
+    FOF_ERR_BAD_STATE = 3,     /* calls out of order (link before build, finalize before link) */
+    FOF_ERR_WORKSPACE = 4,     /* workspace missing, too small or misaligned */
+    FOF_ERR_DEVICE = 5,        /* a HIP runtime call failed */
+    FOF_ERR_UNSUPPORTED = 6    /* valid request this build cannot serve (e.g. too many cells) */
+} fof_status;
+
+typedef enum {
+    FOF_PRED_FP64 = 0,         /* every candidate pair decided with the double predicate */
+    FOF_PRED_FP32_FILTER = 1   /* FP32 decision, double re-decision inside the rounding band */
+} fof_predicate;
+
+typedef struct {
+    int32_t predicate;       /* fof_predicate */
+    int32_t strict_less;     /* 0: link iff r2 <= l2 (default); 1: r2 < l2 */
+    double cell_factor;      /* cell side in units of l_x (>= 1); 0 picks cells of about one
+                                particle each, never narrower than l_x */
+    int32_t collect_stats;   /* 1: count pair tests, links, band hits, CAS retries (slower) */
+    int32_t reserved[7];     /* must be zero */
+} fof_options;
+
+typedef struct {
+    int64_t n_particles;     /* particles in the last build */
+    int64_t n_cells;         /* cells over all boxes */
+    int64_t n_groups;        /* groups over all boxes (after finalize) */
+    int64_t pair_tests;      /* candidate pairs tested        (collect_stats only) */
+    int64_t links;           /* pairs found linked            (collect_stats only) */
+    int64_t band_hits;       /* FP32 results inside the band  (collect_stats only) */
+    int64_t cas_retries;     /* failed compare-and-swaps      (collect_stats only) */
+    int64_t fp64_boxes;      /* boxes the FP32 filter could not serve (decided in double) */
+    int64_t reserved[8];
+} fof_stats;
+
+/* Fills *opt with the defaults: FP32 filter, r2 <= l2, automatic cells, no stats. */
+void fof_default_options(fof_options *opt);
+
+/* Creates a context bound to the current HIP device and to `hip_stream`
+ * (a hipStream_t; NULL = the null stream). `opt` may be NULL for defaults.
+ * Errors: FOF_ERR_INVALID_ARG (null out, bad option), FOF_ERR_DEVICE. */
+fof_status fof_create(fof_ctx **out, const fof_options *opt, void *hip_stream);
+
+/* Re-binds the context to another stream of the same device. */
+fof_status fof_set_stream(fof_ctx *ctx, void *hip_stream);
+
+/* Host only, touches no device memory: validates the box description and
+ * returns in *bytes the workspace the following fof_build_cells needs.
+ * h_box_offsets has n_boxes + 1 non-decreasing entries starting at 0; the
+ * total count must be below 2^31. Each box needs L > 0 finite, 0 < l_x and at
+ * least 3 cells of side >= l_x (1 + 2^-20) per axis (so l_x < L / 3).
+ * Errors: FOF_ERR_INVALID_ARG, FOF_ERR_UNSUPPORTED (more than 2^31 - 2 cells). */
+fof_status fof_workspace_bytes(fof_ctx *ctx, const int64_t *h_box_offsets, const double *h_box,
+                               const double *h_lx, int32_t n_boxes, size_t *bytes);
+
+/* Hands the library a device workspace of `bytes` bytes (256-byte aligned),
+ * owned by the caller and kept alive until the context is destroyed or another
+ * workspace is set. */
+fof_status fof_set_workspace(fof_ctx *ctx, void *d_ws, size_t bytes);
+
+/* Bins the particles into cells (Section 3.1: only cells within l_x of each
+ * other are searched; cells as wide as the linking length work best).
+ * d_pos: [n_total][3] FP32, x y z interleaved, on the device, read only; it
+ * must stay unchanged until fof_link has run. Validates like
+ * fof_workspace_bytes, then checks the workspace (FOF_ERR_WORKSPACE). */
+fof_status fof_build_cells(fof_ctx *ctx, const float *d_pos, const int64_t *h_box_offsets,
+                           const double *h_box, const double *h_lx, int32_t n_boxes);
+
+/* Finds every linked pair among each cell and its 13 half-shell neighbour
+ * cells and merges their groups with lock-free union-find (Section 3.2,
+ * Listing 2, with the compare-and-swap expecting the root value found by the
+ * find). Errors: FOF_ERR_BAD_STATE if no build preceded it. */
+fof_status fof_link(fof_ctx *ctx);
+
+/* Writes, for every particle i (input order), d_group_index[i] = the smallest
+ * box-local index in its group, and d_group_size[i] = the group size if i is
+ * that smallest index (the root), else 0 (Section 3.4). Both are [n_total]
+ * int32 device arrays. If h_n_groups is not NULL it receives the number of
+ * groups of each box ([n_boxes] int64, host) and the call waits for the stream;
+ * a latched coordinate error is returned then. */
+fof_status fof_finalize(fof_ctx *ctx, int32_t *d_group_index, int32_t *d_group_size, int64_t *h_n_groups);
+
+/* Waits for the stream and copies the per-box group counts of the last
+ * finalize (or graph launch) to h_n_groups[n_boxes]; returns a latched error. */
+fof_status fof_read_n_groups(fof_ctx *ctx, int64_t *h_n_groups);
+
+/* Waits for the stream and returns counters of the last run. */
+fof_status fof_get_stats(fof_ctx *ctx, fof_stats *out);
+
+/* Captures build + link + finalize for these exact arguments into a HIP graph
+ * owned by the context (replacing any previous one). The box description is
+ * planned and uploaded before capture, so the graph holds kernel launches
+ * only. fof_graph_launch replays it on the context's stream; the per-box
+ * group counts stay on the device (fof_read_n_groups). */
+fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_box_offsets,
+                             const double *h_box, const double *h_lx, int32_t n_boxes,
+                             int32_t *d_group_index, int32_t *d_group_size);
+fof_status fof_graph_launch(fof_ctx *ctx);
+
+/* Releases the context, its graph and its pinned staging buffer (not the
+ * caller's workspace). Waits for the stream. NULL is accepted. */
+fof_status fof_destroy(fof_ctx *ctx);
+
+/* Static description of a status code. */
+const char *fof_status_string(fof_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOF_H */

@@ -1,0 +1,499 @@
+// C-ABI of the gfx950 Friends-of-Friends library: argument validation, cell
+// geometry, FP32 guard-band thresholds, workspace carve-up, launch sequencing
+// and HIP graph capture. Every compute step runs in fof_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fof.h"
+#include "fof_internal.h"
+
+namespace {
+
+using fof::BoxDev;
+using fof::Counters;
+using fof::Plan;
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxCells = (int64_t)INT32_MAX - 2;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Round a double to FP32 toward -inf / +inf.
+float round_down_f32(double v)
+{
+    float f = (float)v;
+    if ((double)f > v) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+
+float round_up_f32(double v)
+{
+    float f = (float)v;
+    if ((double)f < v) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+struct HostPlan {
+    int32_t n_boxes = 0;
+    int64_t n = 0;
+    int64_t n_cells = 0;
+    int64_t scan_tiles = 0;
+    int64_t fp64_boxes = 0;
+    std::vector<BoxDev> boxes;
+    std::vector<int64_t> p0;
+    // workspace layout (byte offsets)
+    size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_rank = 0, o_sorted = 0,
+           o_perm = 0, o_parent = 0, o_gsize = 0, total = 0;
+
+    bool same_geometry(const HostPlan &o) const
+    {
+        if (n_boxes != o.n_boxes || n != o.n || n_cells != o.n_cells) return false;
+        if (p0 != o.p0) return false;
+        return std::memcmp(boxes.data(), o.boxes.data(), sizeof(BoxDev) * boxes.size()) == 0;
+    }
+};
+
+}  // namespace
+
+struct fof_ctx {
+    fof_options opt{};
+    hipStream_t stream = nullptr;
+    int device = -1;
+
+    HostPlan plan;
+    bool planned = false;
+    bool uploaded = false;     // descriptor table of `plan` is in the workspace
+
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+
+    void *stage = nullptr;     // pinned host staging for the descriptor table
+    size_t stage_bytes = 0;
+
+    int state = 0;             // 0 idle, 1 cells built, 2 linked
+    Plan dev{};                // pointers of the current run
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+fof_status dev_err(hipError_t e) { return e == hipSuccess ? FOF_OK : FOF_ERR_DEVICE; }
+
+bool options_valid(const fof_options &o)
+{
+    if (o.predicate != FOF_PRED_FP64 && o.predicate != FOF_PRED_FP32_FILTER) return false;
+    if (o.strict_less != 0 && o.strict_less != 1) return false;
+    if (!(o.cell_factor == 0.0 || (o.cell_factor >= 1.0 && std::isfinite(o.cell_factor)))) return false;
+    if (o.collect_stats != 0 && o.collect_stats != 1) return false;
+    for (int k = 0; k < 7; ++k)
+        if (o.reserved[k] != 0) return false;
+    return true;
+}
+
+// Cells per axis for one box: as many as the option asks for (cells of about
+// one particle by default), never narrower than l_x (1 + 2^-20), at least 3.
+fof_status cells_per_axis(const fof_options &o, int64_t n_box, double L, double lx, int64_t *nc_out)
+{
+    const double fit = std::floor(L / (lx * (1.0 + 1.0 / 1048576.0)));
+    if (!(fit >= 3.0)) return FOF_ERR_INVALID_ARG;
+    double want;
+    if (o.cell_factor > 0.0) want = std::floor(L / (o.cell_factor * lx));
+    else want = std::floor(std::cbrt((double)(n_box > 1 ? n_box : 1)) + 1e-9);
+    double nc = want < fit ? want : fit;
+    if (nc < 3.0) nc = 3.0;
+    if (nc > 1290.0) return FOF_ERR_UNSUPPORTED;   // nc^3 must stay below 2^31
+    *nc_out = (int64_t)nc;
+    return FOF_OK;
+}
+
+// FP32 decision thresholds. With u = 2^-24 the FP32 squared distance R32 of a
+// pair satisfies (1-u)^5 R <= R32 <= (1+u)^5 R, R being the exact squared
+// minimum-image distance (one rounding per axis difference, three in the
+// sum). The double predicate's value lies within E64 of R. Hence
+//   R32 < lo32 = RD((l2 - E64)(1 - 8u))  =>  r2_64 < l2   (linked), and
+//   R32 > hi32 = RU((l2 + E64)(1 + 8u))  =>  r2_64 > l2   (not linked).
+// The filter is used only where that argument holds: L exact in FP32, l2 and
+// L far from FP32 underflow and overflow.
+void fp32_thresholds(BoxDev &b, double lx)
+{
+    const double U = DBL_EPSILON / 2.0, u = 1.0 / 16777216.0;
+    const double l2 = b.l2;
+    const bool ok = (double)(float)b.L == b.L && l2 >= 0x1p-100 && l2 <= 0x1p100 && b.L <= 0x1p60;
+    b.use_fp64 = ok ? 0 : 1;
+    b.L32 = (float)b.L;
+    if (!ok) {
+        b.lo32 = -1.0f;
+        b.hi32 = -1.0f;
+        return;
+    }
+    const double e = U * b.L;                       // per-axis error of the double difference
+    const double g3 = 3.0 * U / (1.0 - 3.0 * U);
+    const double D = e * (4.0 * std::sqrt(3.0) * lx + 3.0 * e);
+    const double E64 = 2.0 * (g3 * (4.0 * l2 + D) + D);
+    b.lo32 = round_down_f32((l2 - E64) * (1.0 - 8.0 * u));
+    b.hi32 = round_up_f32((l2 + E64) * (1.0 + 8.0 * u));
+}
+
+fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box, const double *lx, int32_t n_boxes,
+                     HostPlan *out)
+{
+    if (!offsets || !box || !lx || n_boxes < 1) return FOF_ERR_INVALID_ARG;
+    if (offsets[0] != 0) return FOF_ERR_INVALID_ARG;
+    HostPlan p;
+    p.n_boxes = n_boxes;
+    p.boxes.resize((size_t)n_boxes);
+    p.p0.assign(offsets, offsets + n_boxes + 1);
+    int64_t cells = 0;
+    for (int32_t k = 0; k < n_boxes; ++k) {
+        const int64_t nb = offsets[k + 1] - offsets[k];
+        if (nb < 0 || offsets[k + 1] > (int64_t)INT32_MAX) return FOF_ERR_INVALID_ARG;
+        const double L = box[k], l = lx[k];
+        if (!(L > 0.0) || !std::isfinite(L) || !(l > 0.0) || !std::isfinite(l)) return FOF_ERR_INVALID_ARG;
+        int64_t nc = 0;
+        fof_status st = cells_per_axis(c->opt, nb, L, l, &nc);
+        if (st != FOF_OK) return st;
+        BoxDev &b = p.boxes[(size_t)k];
+        std::memset(&b, 0, sizeof(b));
+        b.p0 = offsets[k];
+        b.p1 = offsets[k + 1];
+        b.cell_base = cells;
+        b.nc = (int32_t)nc;
+        b.L = L;
+        b.half = 0.5 * L;
+        b.inv_h = (double)nc / L;
+        b.l2 = l * l;
+        fp32_thresholds(b, l);
+        if (c->opt.predicate == FOF_PRED_FP32_FILTER && b.use_fp64) ++p.fp64_boxes;
+        cells += nc * nc * nc;
+        if (cells > kMaxCells) return FOF_ERR_UNSUPPORTED;
+    }
+    p.n = offsets[n_boxes];
+    p.n_cells = cells;
+    p.scan_tiles = fof::scan_tiles_for(cells);
+
+    const size_t n = (size_t)p.n;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + (bytes ? bytes : 1));
+        return at;
+    };
+    p.o_boxes = take(sizeof(BoxDev) * (size_t)n_boxes);
+    p.o_p0 = take(sizeof(int64_t) * ((size_t)n_boxes + 1));
+    p.o_counters = take(sizeof(Counters));
+    p.o_groups = take(sizeof(unsigned long long) * (size_t)n_boxes);
+    p.o_cell = take(sizeof(int32_t) * ((size_t)cells + 1));
+    p.o_part = take(sizeof(int32_t) * (size_t)p.scan_tiles);
+    p.o_rank = take(sizeof(int32_t) * n);
+    p.o_sorted = take(sizeof(float) * 4 * n);
+    p.o_perm = take(sizeof(int32_t) * 2 * n);
+    p.o_parent = take(sizeof(int32_t) * n);
+    p.o_gsize = take(sizeof(int32_t) * n);
+    p.total = o;
+    *out = std::move(p);
+    return FOF_OK;
+}
+
+fof_status ensure_device(fof_ctx *c)
+{
+    if (c->device >= 0) return FOF_OK;
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess || d < 0) return FOF_ERR_DEVICE;
+    c->device = d;
+    return FOF_OK;
+}
+
+template <typename T>
+T *at(void *base, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+// Adopt `np` as the current plan; upload its descriptor table if it changed.
+fof_status install_plan(fof_ctx *c, HostPlan &&np)
+{
+    if (!c->ws) return FOF_ERR_WORKSPACE;
+    if (c->ws_bytes < np.total) return FOF_ERR_WORKSPACE;
+    fof_status st = ensure_device(c);
+    if (st != FOF_OK) return st;
+    const bool same = c->planned && c->uploaded && c->plan.same_geometry(np);
+    if (!same) {
+        const size_t table = np.o_counters;   // boxes + p0 region
+        // the staging buffer may still feed an earlier, in-flight copy
+        if (c->stage && hipStreamSynchronize(c->stream) != hipSuccess) return FOF_ERR_DEVICE;
+        if (c->stage_bytes < table) {
+            if (c->stage) (void)hipHostFree(c->stage);
+            c->stage = nullptr;
+            c->stage_bytes = 0;
+            if (hipHostMalloc(&c->stage, table, hipHostMallocDefault) != hipSuccess) return FOF_ERR_DEVICE;
+            c->stage_bytes = table;
+        }
+        std::memset(c->stage, 0, table);
+        std::memcpy(at<char>(c->stage, np.o_boxes), np.boxes.data(), sizeof(BoxDev) * np.boxes.size());
+        std::memcpy(at<char>(c->stage, np.o_p0), np.p0.data(), sizeof(int64_t) * np.p0.size());
+        hipError_t e = hipMemcpyAsync(c->ws, c->stage, table, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return FOF_ERR_DEVICE;
+        c->uploaded = true;
+    }
+    c->plan = std::move(np);
+    c->planned = true;
+
+    const HostPlan &p = c->plan;
+    Plan &d = c->dev;
+    d.n = p.n;
+    d.n_cells = p.n_cells;
+    d.n_boxes = p.n_boxes;
+    d.predicate = c->opt.predicate;
+    d.strict = c->opt.strict_less;
+    d.stats = c->opt.collect_stats;
+    d.scan_tiles = p.scan_tiles;
+    d.boxes = at<BoxDev>(c->ws, p.o_boxes);
+    d.box_p0 = at<int64_t>(c->ws, p.o_p0);
+    d.counters = at<Counters>(c->ws, p.o_counters);
+    d.n_groups = at<unsigned long long>(c->ws, p.o_groups);
+    d.cell = at<int32_t>(c->ws, p.o_cell);
+    d.scan_part = at<int32_t>(c->ws, p.o_part);
+    d.rank = at<int32_t>(c->ws, p.o_rank);
+    d.sorted = at<float4>(c->ws, p.o_sorted);
+    d.perm = at<int2>(c->ws, p.o_perm);
+    d.parent = at<int32_t>(c->ws, p.o_parent);
+    d.gsize = at<int32_t>(c->ws, p.o_gsize);
+    return FOF_OK;
+}
+
+fof_status do_build(fof_ctx *c, const float *d_pos, const int64_t *off, const double *box, const double *lx,
+                    int32_t n_boxes)
+{
+    HostPlan np;
+    fof_status st = make_plan(c, off, box, lx, n_boxes, &np);
+    if (st != FOF_OK) return st;
+    if (!d_pos && np.n > 0) return FOF_ERR_INVALID_ARG;
+    st = install_plan(c, std::move(np));
+    if (st != FOF_OK) return st;
+    c->dev.pos = d_pos;
+    return FOF_OK;
+}
+
+fof_status enqueue_build(fof_ctx *c, hipStream_t s)
+{
+    hipError_t e = fof::launch_clear(c->dev, s);
+    if (e == hipSuccess) e = fof::launch_build(c->dev, s);
+    return dev_err(e);
+}
+
+fof_status read_back(fof_ctx *c, int64_t *h_n_groups, Counters *h_counters)
+{
+    const HostPlan &p = c->plan;
+    std::vector<unsigned long long> g((size_t)p.n_boxes);
+    Counters cnt{};
+    if (hipMemcpyAsync(g.data(), c->dev.n_groups, sizeof(unsigned long long) * g.size(), hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess)
+        return FOF_ERR_DEVICE;
+    if (hipMemcpyAsync(&cnt, c->dev.counters, sizeof(Counters), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return FOF_ERR_DEVICE;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return FOF_ERR_DEVICE;
+    if (h_n_groups)
+        for (size_t k = 0; k < g.size(); ++k) h_n_groups[k] = (int64_t)g[k];
+    if (h_counters) *h_counters = cnt;
+    return (cnt.error & 1u) ? FOF_ERR_OUT_OF_BOX : FOF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fof_default_options(fof_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->predicate = FOF_PRED_FP32_FILTER;
+}
+
+fof_status fof_create(fof_ctx **out, const fof_options *opt, void *hip_stream)
+{
+    if (!out) return FOF_ERR_INVALID_ARG;
+    *out = nullptr;
+    fof_options o;
+    fof_default_options(&o);
+    if (opt) o = *opt;
+    if (!options_valid(o)) return FOF_ERR_INVALID_ARG;
+    fof_ctx *c = new (std::nothrow) fof_ctx();
+    if (!c) return FOF_ERR_DEVICE;
+    c->opt = o;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return FOF_OK;
+}
+
+fof_status fof_set_stream(fof_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return FOF_ERR_INVALID_ARG;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return FOF_OK;
+}
+
+fof_status fof_workspace_bytes(fof_ctx *ctx, const int64_t *h_box_offsets, const double *h_box, const double *h_lx,
+                               int32_t n_boxes, size_t *bytes)
+{
+    if (!ctx || !bytes) return FOF_ERR_INVALID_ARG;
+    HostPlan p;
+    fof_status st = make_plan(ctx, h_box_offsets, h_box, h_lx, n_boxes, &p);
+    if (st != FOF_OK) return st;
+    *bytes = p.total;
+    return FOF_OK;
+}
+
+fof_status fof_set_workspace(fof_ctx *ctx, void *d_ws, size_t bytes)
+{
+    if (!ctx) return FOF_ERR_INVALID_ARG;
+    if (d_ws && (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) return FOF_ERR_WORKSPACE;
+    if (ctx->ws != d_ws) ctx->uploaded = false;
+    ctx->ws = d_ws;
+    ctx->ws_bytes = d_ws ? bytes : 0;
+    ctx->state = 0;
+    return FOF_OK;
+}
+
+fof_status fof_build_cells(fof_ctx *ctx, const float *d_pos, const int64_t *h_box_offsets, const double *h_box,
+                           const double *h_lx, int32_t n_boxes)
+{
+    if (!ctx) return FOF_ERR_INVALID_ARG;
+    fof_status st = do_build(ctx, d_pos, h_box_offsets, h_box, h_lx, n_boxes);
+    if (st != FOF_OK) return st;
+    st = enqueue_build(ctx, ctx->stream);
+    ctx->state = st == FOF_OK ? 1 : 0;
+    return st;
+}
+
+fof_status fof_link(fof_ctx *ctx)
+{
+    if (!ctx) return FOF_ERR_INVALID_ARG;
+    if (ctx->state != 1) return FOF_ERR_BAD_STATE;
+    fof_status st = dev_err(fof::launch_link(ctx->dev, ctx->stream));
+    ctx->state = st == FOF_OK ? 2 : 0;
+    return st;
+}
+
+fof_status fof_finalize(fof_ctx *ctx, int32_t *d_group_index, int32_t *d_group_size, int64_t *h_n_groups)
+{
+    if (!ctx) return FOF_ERR_INVALID_ARG;
+    if (ctx->state != 2) return FOF_ERR_BAD_STATE;
+    if ((!d_group_index || !d_group_size) && ctx->plan.n > 0) return FOF_ERR_INVALID_ARG;
+    ctx->dev.label = d_group_index;
+    ctx->dev.size = d_group_size;
+    fof_status st = dev_err(fof::launch_finalize(ctx->dev, ctx->stream));
+    ctx->state = 0;   // the forest is consumed: a new build is needed
+    if (st != FOF_OK) return st;
+    if (h_n_groups) return read_back(ctx, h_n_groups, nullptr);
+    return FOF_OK;
+}
+
+fof_status fof_read_n_groups(fof_ctx *ctx, int64_t *h_n_groups)
+{
+    if (!ctx || !h_n_groups) return FOF_ERR_INVALID_ARG;
+    if (!ctx->planned || !ctx->uploaded) return FOF_ERR_BAD_STATE;
+    return read_back(ctx, h_n_groups, nullptr);
+}
+
+fof_status fof_get_stats(fof_ctx *ctx, fof_stats *out)
+{
+    if (!ctx || !out) return FOF_ERR_INVALID_ARG;
+    std::memset(out, 0, sizeof(*out));
+    if (!ctx->planned || !ctx->uploaded) return FOF_ERR_BAD_STATE;
+    std::vector<int64_t> g((size_t)ctx->plan.n_boxes);
+    Counters cnt{};
+    fof_status st = read_back(ctx, g.data(), &cnt);
+    out->n_particles = ctx->plan.n;
+    out->n_cells = ctx->plan.n_cells;
+    for (int64_t v : g) out->n_groups += v;
+    out->pair_tests = (int64_t)cnt.pair_tests;
+    out->links = (int64_t)cnt.links;
+    out->band_hits = (int64_t)cnt.band_hits;
+    out->cas_retries = (int64_t)cnt.cas_retries;
+    out->fp64_boxes = ctx->plan.fp64_boxes;
+    return st;
+}
+
+fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_box_offsets, const double *h_box,
+                             const double *h_lx, int32_t n_boxes, int32_t *d_group_index, int32_t *d_group_size)
+{
+    if (!ctx) return FOF_ERR_INVALID_ARG;
+    fof_status st = do_build(ctx, d_pos, h_box_offsets, h_box, h_lx, n_boxes);
+    if (st != FOF_OK) return st;
+    if ((!d_group_index || !d_group_size) && ctx->plan.n > 0) return FOF_ERR_INVALID_ARG;
+    ctx->dev.label = d_group_index;
+    ctx->dev.size = d_group_size;
+    if (ctx->exec) {
+        (void)hipGraphExecDestroy(ctx->exec);
+        ctx->exec = nullptr;
+    }
+    if (ctx->graph) {
+        (void)hipGraphDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    // the descriptor upload above is ordered on ctx->stream; capture on a
+    // private stream that first waits for it
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return FOF_ERR_DEVICE;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return FOF_ERR_DEVICE;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        e = fof::launch_clear(ctx->dev, cs);
+        if (e == hipSuccess) e = fof::launch_build(ctx->dev, cs);
+        if (e == hipSuccess) e = fof::launch_link(ctx->dev, cs);
+        if (e == hipSuccess) e = fof::launch_finalize(ctx->dev, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) {
+            ctx->graph = g;
+            e = hipGraphInstantiate(&ctx->exec, g, nullptr, nullptr, 0);
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    ctx->state = 0;
+    return dev_err(e);
+}
+
+fof_status fof_graph_launch(fof_ctx *ctx)
+{
+    if (!ctx) return FOF_ERR_INVALID_ARG;
+    if (!ctx->exec) return FOF_ERR_BAD_STATE;
+    return dev_err(hipGraphLaunch(ctx->exec, ctx->stream));
+}
+
+fof_status fof_destroy(fof_ctx *ctx)
+{
+    if (!ctx) return FOF_OK;
+    if (ctx->device >= 0) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    delete ctx;
+    return FOF_OK;
+}
+
+const char *fof_status_string(fof_status s)
+{
+    switch (s) {
+    case FOF_OK: return "ok";
+    case FOF_ERR_INVALID_ARG: return "invalid argument";
+    case FOF_ERR_OUT_OF_BOX: return "coordinate not finite or outside [0, L)";
+    case FOF_ERR_BAD_STATE: return "calls out of order";
+    case FOF_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case FOF_ERR_DEVICE: return "HIP runtime error";
+    case FOF_ERR_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal types shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fof {
+
+// Per-box parameters as the kernels see them (one entry per box).
+struct BoxDev {
+    int64_t p0, p1;       // particle range [p0, p1): input and sorted order use the same range
+    int64_t cell_base;    // first global cell index of the box
+    int32_t nc;           // cells per axis (>= 3)
+    int32_t use_fp64;     // 1: this box is decided in double for every candidate pair
+    double L;             // box side
+    double half;          // L / 2
+    double inv_h;         // nc / L
+    double l2;            // l_x * l_x, rounded once
+    float L32;            // L as FP32 (equal to L whenever the FP32 filter is used)
+    float lo32;           // FP32 r2 below this: linked (proven)
+    float hi32;           // FP32 r2 above this: not linked (proven)
+    float pad;
+};
+
+// Device counters (one block of the workspace, cleared by every build).
+struct Counters {
+    unsigned long long pair_tests;
+    unsigned long long links;
+    unsigned long long band_hits;
+    unsigned long long cas_retries;
+    unsigned int error;         // bit 0: coordinate outside [0, L) or not finite
+    unsigned int pad[7];
+};
+
+// Everything a launch needs: raw pointers into the caller's workspace.
+struct Plan {
+    int64_t n;              // particles over all boxes
+    int64_t n_cells;        // cells over all boxes
+    int32_t n_boxes;
+    int32_t predicate;      // 0 fp64, 1 fp32 filter
+    int32_t strict;         // 1: r2 < l2
+    int32_t stats;          // 1: count pair tests etc.
+    int64_t scan_tiles;     // tiles of the cell-count scan
+
+    const float *pos;       // [n][3] input
+    const BoxDev *boxes;    // [n_boxes]
+    const int64_t *box_p0;  // [n_boxes + 1] particle offsets
+
+    int32_t *cell;          // [n_cells + 1] counts, then exclusive prefix (cell start)
+    int32_t *scan_part;     // [scan_tiles] tile sums
+    int32_t *rank;          // [n] slot of particle i inside its cell
+    float4 *sorted;         // [n] cell-sorted x, y, z
+    int2 *perm;             // [n] .x original index of sorted particle s, .y group minimum (at roots)
+    int32_t *parent;        // [n] union-find forest over sorted indices
+    int32_t *gsize;         // [n] group member count at roots (sorted indices)
+    unsigned long long *n_groups;  // [n_boxes]
+    Counters *counters;
+
+    int32_t *label;         // [n] output, input order
+    int32_t *size;          // [n] output, input order
+};
+
+// Tiles of the cell-count scan for n_cells cells (fof_kernels.hip).
+int64_t scan_tiles_for(int64_t n_cells);
+
+// Kernel launchers (fof_kernels.hip). All enqueue on `stream`.
+hipError_t launch_clear(const Plan &p, hipStream_t stream);
+hipError_t launch_build(const Plan &p, hipStream_t stream);
+hipError_t launch_link(const Plan &p, hipStream_t stream);
+hipError_t launch_finalize(const Plan &p, hipStream_t stream);
+
+}  // namespace fof

@@ -1,0 +1,145 @@
+"""The C-ABI library on the CPU: it loads, exports every function that
+include/fof.h declares, and rejects bad arguments on the host before touching
+a device (no compute call is made here)."""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+import paper_2003_11468_amd as fof
+
+
+def declared_functions():
+    text = open(fof.HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(fof_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = fof.load_library()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(fof.EXPORTS)
+
+
+def test_status_strings():
+    for s in range(7):
+        assert fof.fof_status_string(s)
+    assert fof.fof_status_string(0) == "ok"
+
+
+def test_default_options():
+    o = fof.fof_default_options()
+    assert o.predicate == fof.FOF_PRED_FP32_FILTER and o.strict_less == 0 and o.cell_factor == 0.0
+
+
+def _ctx(**kw):
+    return fof.fof_create(fof.make_options(**kw))
+
+
+def test_create_rejects_bad_options():
+    for kw in (dict(cell_factor=0.5), dict(cell_factor=float("inf"))):
+        with pytest.raises(fof.FoFError) as e:
+            _ctx(**kw)
+        assert e.value.status == fof.FOF_ERR_INVALID_ARG
+    o = fof.fof_default_options()
+    o.predicate = 7
+    with pytest.raises(fof.FoFError):
+        fof.fof_create(o)
+    o = fof.fof_default_options()
+    o.reserved[3] = 1
+    with pytest.raises(fof.FoFError):
+        fof.fof_create(o)
+
+
+def test_workspace_bytes_scales_with_particles_and_cells():
+    ctx = _ctx()
+    try:
+        small = fof.fof_workspace_bytes(ctx, [0, 1000], 1.0, 0.02)
+        big = fof.fof_workspace_bytes(ctx, [0, 100000], 1.0, 0.002)
+        assert big > small > 1000 * 36
+        two = fof.fof_workspace_bytes(ctx, [0, 1000, 3000], [1.0, 2.0], [0.02, 0.03])
+        assert two > small
+        assert fof.fof_workspace_bytes(ctx, [0, 0], 1.0, 0.1) > 0          # empty box
+    finally:
+        fof.fof_destroy(ctx)
+
+
+@pytest.mark.parametrize("offsets,box,lx", [
+    ([0, 10], 1.0, 0.0),                 # l_x <= 0
+    ([0, 10], 1.0, -0.1),
+    ([0, 10], 1.0, float("nan")),
+    ([0, 10], 0.0, 0.1),                 # L <= 0
+    ([0, 10], float("inf"), 0.1),
+    ([0, 10], 1.0, 0.34),                # fewer than 3 cells of side >= l_x
+    ([1, 10], 1.0, 0.1),                 # offsets must start at 0
+    ([0, 10, 5], [1.0, 1.0], [0.1, 0.1]),  # decreasing offsets
+    ([0, 2 ** 31], 1.0, 0.1),            # too many particles
+])
+def test_host_validation(offsets, box, lx):
+    ctx = _ctx()
+    try:
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_workspace_bytes(ctx, offsets, box, lx)
+        assert e.value.status == fof.FOF_ERR_INVALID_ARG
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_build_cells(ctx, None, offsets, box, lx)
+        assert e.value.status == fof.FOF_ERR_INVALID_ARG
+    finally:
+        fof.fof_destroy(ctx)
+
+
+def test_too_many_cells_is_unsupported():
+    ctx = _ctx(cell_factor=1.0)
+    try:
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_workspace_bytes(ctx, [0, 10 ** 9], 1.0, 1e-4)
+        assert e.value.status == fof.FOF_ERR_UNSUPPORTED
+    finally:
+        fof.fof_destroy(ctx)
+
+
+def test_call_order_and_missing_workspace():
+    ctx = _ctx()
+    try:
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_link(ctx)
+        assert e.value.status == fof.FOF_ERR_BAD_STATE
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_finalize(ctx, None, None)
+        assert e.value.status == fof.FOF_ERR_BAD_STATE
+        with pytest.raises(fof.FoFError) as e:       # valid boxes, no workspace set
+            fof.fof_build_cells(ctx, None, [0, 0], 1.0, 0.1)
+        assert e.value.status == fof.FOF_ERR_WORKSPACE
+        with pytest.raises(fof.FoFError) as e:       # misaligned workspace pointer
+            fof.load_library()
+            st = fof.load_library().fof_set_workspace(ctx, ctypes.c_void_p(0x1001), 4096)
+            fof._check(st, "fof_set_workspace")
+        assert e.value.status == fof.FOF_ERR_WORKSPACE
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_graph_launch(ctx)
+        assert e.value.status == fof.FOF_ERR_BAD_STATE
+        with pytest.raises(fof.FoFError):
+            fof.fof_read_n_groups(ctx, 1)
+    finally:
+        fof.fof_destroy(ctx)
+
+
+def test_null_arguments():
+    lib = fof.load_library()
+    assert lib.fof_create(None, None, None) == fof.FOF_ERR_INVALID_ARG
+    assert lib.fof_link(None) == fof.FOF_ERR_INVALID_ARG
+    assert lib.fof_destroy(None) == fof.FOF_OK
+    ctx = _ctx()
+    try:
+        assert lib.fof_workspace_bytes(ctx, None, None, None, 1, None) == fof.FOF_ERR_INVALID_ARG
+        off = np.array([0, 4], dtype=np.int64)
+        L = np.ones(1)
+        assert lib.fof_build_cells(ctx, None, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   L.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   (L * 0.1).ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1) \
+            == fof.FOF_ERR_INVALID_ARG          # 4 particles but no position pointer
+    finally:
+        fof.fof_destroy(ctx)

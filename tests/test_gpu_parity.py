@@ -1,0 +1,255 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Labels (group minimum index), sizes and group counts are integers, so every
+comparison is exact, element by element. Both link predicates must give the
+oracle's result; the FP32 filter is exact by construction of its guard band.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from cases import chain_across_boundary, lattice, load_fixture
+
+torch = pytest.importorskip("torch")
+fof = pytest.importorskip("paper_2003_11468_amd")
+
+pytestmark = pytest.mark.gpu
+PREDICATES = ["fp32_filter", "fp64"]
+
+
+def gpu_run(pos, offsets, box, lx, predicate="fp32_filter", strict=False, cell_factor=0.0, stats=False):
+    f = fof.FoF(predicate, strict, cell_factor, stats)
+    try:
+        p = torch.from_numpy(np.ascontiguousarray(pos, dtype=np.float32)).cuda()
+        label, size, ng = f.run(p, offsets, box, lx)
+        st = f.stats() if stats else None
+        return label.cpu().numpy(), size.cpu().numpy(), ng, st
+    finally:
+        f.close()
+
+
+def assert_single(pos, lx, box=1.0, strict=False, predicate="fp32_filter", cell_factor=0.0):
+    ref = oracle.fof(pos, lx, box, strict=strict)
+    lab, size, ng, _ = gpu_run(pos, [0, len(pos)], box, lx, predicate, strict, cell_factor)
+    assert np.array_equal(lab, ref[0])
+    assert np.array_equal(size, ref[1])
+    assert int(ng[0]) == ref[2]
+    return ref
+
+
+# ----------------------------------------------------------- hand cases --
+
+@pytest.mark.parametrize("predicate", PREDICATES)
+@pytest.mark.parametrize("strict", [False, True])
+def test_golden_fixture(predicate, strict):
+    fx = load_fixture("fig2_indirect_u.txt")
+    tag = "lt" if strict else "le"
+    lab, size, ng, _ = gpu_run(fx["pos"], [0, len(fx["pos"])], fx["box"], fx["lx"], predicate, strict)
+    assert np.array_equal(lab, fx["labels_" + tag])
+    assert np.array_equal(size, fx["sizes_" + tag])
+    assert int(ng[0]) == int(fx["groups_" + tag][0])
+
+
+@pytest.mark.parametrize("predicate", PREDICATES)
+def test_lattice_below_and_above_spacing(predicate):
+    pos = lattice(16, seed=3)
+    lab, _, ng, _ = gpu_run(pos, [0, len(pos)], 1.0, (1 - 1e-3) / 16, predicate)
+    assert int(ng[0]) == 16 ** 3 and np.array_equal(lab, np.arange(16 ** 3))
+    lab, size, ng, _ = gpu_run(pos, [0, len(pos)], 1.0, (1 + 1e-3) / 16, predicate)
+    assert int(ng[0]) == 1 and np.all(lab == 0) and size[0] == 16 ** 3
+
+
+@pytest.mark.parametrize("predicate", PREDICATES)
+@pytest.mark.parametrize("strict,groups", [(False, 1), (True, 64 ** 3)])
+def test_dyadic_tie_lattice(predicate, strict, groups):
+    pos = lattice(64, seed=1)
+    lab, size, ng, _ = gpu_run(pos, [0, len(pos)], 1.0, 2.0 ** -6, predicate, strict)
+    assert int(ng[0]) == groups
+    if groups == 1:
+        assert np.all(lab == 0) and size[0] == 64 ** 3
+
+
+@pytest.mark.parametrize("predicate", PREDICATES)
+def test_chains_across_each_face(predicate):
+    for axis in range(3):
+        pos = chain_across_boundary(40, 0.0234375, axis)
+        assert_single(pos, 0.03125, predicate=predicate)
+        assert_single(pos, 0.0234375 * (1 - 1e-3), predicate=predicate)
+
+
+@pytest.mark.parametrize("predicate", PREDICATES)
+def test_edge_cases(predicate):
+    lab, size, ng, _ = gpu_run(np.zeros((0, 3), np.float32), [0, 0], 1.0, 0.1, predicate)
+    assert len(lab) == 0 and int(ng[0]) == 0
+    lab, size, ng, _ = gpu_run(np.float32([[0.3, 0.3, 0.3]]), [0, 1], 1.0, 0.1, predicate)
+    assert list(lab) == [0] and list(size) == [1] and int(ng[0]) == 1
+    pos = np.float32([[0.3, 0.3, 0.3], [0.9, 0.9, 0.9], [0.3, 0.3, 0.3]])
+    lab, size, ng, _ = gpu_run(pos, [0, 3], 1.0, 1e-6, predicate)
+    assert list(lab) == [0, 1, 0] and list(size) == [2, 1, 0] and int(ng[0]) == 2
+
+
+def test_out_of_box_coordinate_is_reported():
+    pos = synth.uniform(1000, 5)
+    pos[17, 2] = 1.0
+    p = torch.from_numpy(pos).cuda()
+    f = fof.FoF()
+    try:
+        with pytest.raises(fof.FoFError) as e:
+            f.run(p, [0, 1000], 1.0, 0.02)
+        assert e.value.status == fof.FOF_ERR_OUT_OF_BOX
+        pos[17, 2] = np.nan
+        p = torch.from_numpy(pos).cuda()
+        with pytest.raises(fof.FoFError) as e:
+            f.run(p, [0, 1000], 1.0, 0.02)
+        assert e.value.status == fof.FOF_ERR_OUT_OF_BOX
+        pos[17, 2] = 0.5                         # a clean run afterwards clears the latch
+        p = torch.from_numpy(pos).cuda()
+        f.run(p, [0, 1000], 1.0, 0.02)
+    finally:
+        f.close()
+
+
+# ------------------------------------------------------- seeded random --
+
+@pytest.mark.parametrize("predicate", PREDICATES)
+@pytest.mark.parametrize("n", [2, 63, 64, 65, 257, 1000, 4097, 65537])
+def test_uniform_sizes(predicate, n):
+    pos = synth.uniform(n, 40 + n)
+    assert_single(pos, synth.linking_length(0.6, n) if n > 27 else 0.2, predicate=predicate)
+
+
+@pytest.mark.parametrize("predicate", PREDICATES)
+@pytest.mark.parametrize("b", [0.2, 0.5, 0.9, 1.5])
+def test_clustered_linking_lengths(predicate, b):
+    n = 200003
+    pos = synth.clustered(n, 77, 0, 0.6)
+    lx = synth.linking_length(b, n)
+    if lx * (1 + 2 ** -20) * 3 > 1.0:
+        pytest.skip("fewer than 3 cells")
+    assert_single(pos, lx, predicate=predicate)
+
+
+@pytest.mark.parametrize("cell_factor", [1.0, 1.5, 2.0, 3.0, 7.0])
+def test_cell_sizes(cell_factor):
+    n = 150000
+    pos = synth.clustered(n, 5, 0, 0.6)
+    lx = synth.linking_length(0.2, n)
+    for predicate in PREDICATES:
+        assert_single(pos, lx, predicate=predicate, cell_factor=cell_factor)
+
+
+def test_uniform32k_and_strict():
+    w = synth.make("uniform32k")
+    for predicate in PREDICATES:
+        for strict in (False, True):
+            assert_single(w.pos, float(w.lx[0]), strict=strict, predicate=predicate)
+
+
+def test_box_side_other_than_one():
+    pos = (synth.clustered(50000, 8, 0, 0.6).astype(np.float64) * 8.0).astype(np.float32)  # exact scaling
+    lx = synth.linking_length(0.3, 50000, box=8.0)
+    for predicate in PREDICATES:
+        assert_single(pos, lx, box=8.0, predicate=predicate)
+
+
+def test_box_side_not_exact_in_fp32_falls_back_to_fp64():
+    L = 0.1
+    pos = np.minimum(synth.uniform(20000, 3).astype(np.float64) * L, np.nextafter(L, 0)).astype(np.float32)
+    pos = np.where(pos.astype(np.float64) >= L, np.float32(0), pos).astype(np.float32)
+    lx = synth.linking_length(0.7, 20000, box=L)
+    ref = oracle.fof(pos, lx, L)
+    lab, size, ng, st = gpu_run(pos, [0, len(pos)], L, lx, "fp32_filter", stats=True)
+    assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1])
+    assert st["fp64_boxes"] == 1
+
+
+# -------------------------------------------------------------- batched --
+
+@pytest.mark.parametrize("predicate", PREDICATES)
+def test_batched_boxes(predicate):
+    w = synth.make("batched256", n_boxes=24, size_scale=0.05)
+    sizes = np.diff(w.offsets)
+    sizes[3] = 0                      # an empty box
+    sizes[7] = 1                      # a single particle
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = np.concatenate([w.pos[w.offsets[k]:w.offsets[k] + sizes[k]] for k in range(24)])
+    ref = oracle.fof_boxes(pos, offsets, w.box, w.lx)
+    lab, size, ng, _ = gpu_run(pos, offsets, w.box, w.lx, predicate)
+    assert np.array_equal(lab, ref[0])
+    assert np.array_equal(size, ref[1])
+    assert np.array_equal(ng, ref[2])
+
+
+def test_graph_replays_match_eager():
+    w = synth.make("batched256", n_boxes=16, size_scale=0.03)
+    ref = oracle.fof_boxes(w.pos, w.offsets, w.box, w.lx)
+    f = fof.FoF()
+    try:
+        p = torch.from_numpy(w.pos).cuda()
+        label, size = f.outputs(w.n)
+        f.capture(p, w.offsets, w.box, w.lx, label, size)
+        for rep in range(4):
+            label.fill_(-7)
+            size.fill_(-7)
+            f.replay()
+            ng = f.n_groups(w.n_boxes)
+            assert np.array_equal(label.cpu().numpy(), ref[0]), rep
+            assert np.array_equal(size.cpu().numpy(), ref[1]), rep
+            assert np.array_equal(ng, ref[2]), rep
+            # eager work on the same stream between replays
+            lab2, size2, ng2 = f.run(p[: w.offsets[3]].contiguous(), w.offsets[:4], w.box[:3], w.lx[:3])
+            assert np.array_equal(lab2.cpu().numpy(), ref[0][: w.offsets[3]])
+            f.capture(p, w.offsets, w.box, w.lx, label, size)
+    finally:
+        f.close()
+
+
+# ---------------------------------------------------------- properties --
+
+def test_repeated_runs_identical():
+    n = 300000
+    pos = synth.clustered(n, 99, 0, 0.6)
+    lx = synth.linking_length(0.5, n)
+    first = gpu_run(pos, [0, n], 1.0, lx)
+    for _ in range(5):
+        again = gpu_run(pos, [0, n], 1.0, lx)
+        assert np.array_equal(first[0], again[0]) and np.array_equal(first[1], again[1])
+
+
+def test_stats_count_band_and_links():
+    n = 100000
+    pos = synth.clustered(n, 12, 0, 0.6)
+    lx = synth.linking_length(0.2, n)
+    ref = oracle.fof(pos, lx)
+    lab, size, ng, st = gpu_run(pos, [0, n], 1.0, lx, "fp32_filter", stats=True)
+    assert np.array_equal(lab, ref[0])
+    assert st["pair_tests"] > st["links"] >= n - ref[2]
+    assert 0 <= st["band_hits"] < max(10, st["links"] // 1000)
+    assert st["n_groups"] == ref[2]
+
+
+def test_near_threshold_pairs_fp32_filter_is_exact():
+    """Pairs at distances within a few FP32 ulps of l_x, several orientations
+    and periodic wraps: the filter must reproduce the double decision."""
+    rng = np.random.default_rng(2024)
+    m = 20000
+    lx = 0.01
+    a = rng.uniform(0, 1, size=(m, 3))
+    d = rng.normal(size=(m, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rel = rng.choice([-4e-7, -2e-7, -6e-8, 0.0, 6e-8, 2e-7, 4e-7], size=m) + rng.normal(0, 1e-7, size=m)
+    b = np.mod(a + d * lx * (1 + rel)[:, None], 1.0)
+    pos = np.empty((2 * m, 3), dtype=np.float32)
+    pos[0::2] = a.astype(np.float32)
+    pos[1::2] = b.astype(np.float32)
+    pos[pos >= 1.0] = 0.0
+    ref = oracle.fof(pos, lx)
+    for predicate in PREDICATES:
+        lab, size, ng, st = gpu_run(pos, [0, 2 * m], 1.0, lx, predicate, stats=(predicate == "fp32_filter"))
+        assert np.array_equal(lab, ref[0]), predicate
+        assert np.array_equal(size, ref[1]), predicate
+        if st is not None:
+            assert st["band_hits"] > 0
