@@ -76,7 +76,10 @@ typedef struct {
     double cell_factor;      /* cell side in units of l_x (>= 1); 0 picks cells of about one
                                 particle each, never narrower than l_x */
     int32_t collect_stats;   /* 1: count pair tests, links, band hits, CAS retries (slower) */
-    int32_t reserved[7];     /* must be zero */
+    int32_t dense_min;       /* cells holding at least this many particles are searched by whole
+                                wavefronts (64 particles against broadcast candidates); the others
+                                per particle. 0 = default (32) */
+    int32_t reserved[6];     /* must be zero */
 } fof_options;
 
 typedef struct {

@@ -37,7 +37,7 @@ class FoFError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("predicate", ctypes.c_int32), ("strict_less", ctypes.c_int32), ("cell_factor", ctypes.c_double),
-                ("collect_stats", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("collect_stats", ctypes.c_int32), ("dense_min", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class Stats(ctypes.Structure):
@@ -206,12 +206,13 @@ def fof_status_string(status: int) -> str:
 # ------------------------------------------------------ tensor wrapper --
 
 def make_options(predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
-                 stats: bool = False) -> Options:
+                 stats: bool = False, dense_min: int = 0) -> Options:
     o = fof_default_options()
     o.predicate = PREDICATES[predicate]
     o.strict_less = int(strict)
     o.cell_factor = float(cell_factor)
     o.collect_stats = int(stats)
+    o.dense_min = int(dense_min)
     return o
 
 
@@ -219,12 +220,12 @@ class FoF:
     """A context plus a workspace tensor, reused across calls of the same shape."""
 
     def __init__(self, predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
-                 stats: bool = False, stream=None):
+                 stats: bool = False, stream=None, dense_min: int = 0):
         import torch
 
         self._torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats), self.stream.cuda_stream)
+        self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats, dense_min), self.stream.cuda_stream)
         self.ws = None
 
     def close(self):

@@ -44,11 +44,12 @@ struct HostPlan {
     int64_t n_cells = 0;
     int64_t scan_tiles = 0;
     int64_t fp64_boxes = 0;
+    int64_t max_items = 0;
     std::vector<BoxDev> boxes;
     std::vector<int64_t> p0;
     // workspace layout (byte offsets)
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_rank = 0, o_sorted = 0,
-           o_perm = 0, o_parent = 0, o_gsize = 0, total = 0;
+           o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, total = 0;
 
     bool same_geometry(const HostPlan &o) const
     {
@@ -92,7 +93,8 @@ bool options_valid(const fof_options &o)
     if (o.strict_less != 0 && o.strict_less != 1) return false;
     if (!(o.cell_factor == 0.0 || (o.cell_factor >= 1.0 && std::isfinite(o.cell_factor)))) return false;
     if (o.collect_stats != 0 && o.collect_stats != 1) return false;
-    for (int k = 0; k < 7; ++k)
+    if (o.dense_min < 0) return false;
+    for (int k = 0; k < 6; ++k)
         if (o.reserved[k] != 0) return false;
     return true;
 }
@@ -128,9 +130,9 @@ void fp32_thresholds(BoxDev &b, double lx)
     const bool ok = (double)(float)b.L == b.L && l2 >= 0x1p-100 && l2 <= 0x1p100 && b.L <= 0x1p60;
     b.use_fp64 = ok ? 0 : 1;
     b.L32 = (float)b.L;
-    if (!ok) {
-        b.lo32 = -1.0f;
-        b.hi32 = -1.0f;
+    if (!ok) {   // every pair falls in the band: decided in double
+        b.lo32 = -INFINITY;
+        b.hi32 = INFINITY;
         return;
     }
     const double e = U * b.L;                       // per-axis error of the double difference
@@ -140,6 +142,11 @@ void fp32_thresholds(BoxDev &b, double lx)
     b.lo32 = round_down_f32((l2 - E64) * (1.0 - 8.0 * u));
     b.hi32 = round_up_f32((l2 + E64) * (1.0 + 8.0 * u));
 }
+
+constexpr int kDefaultDenseMin = 32;
+constexpr int kDenseBlocks = 2048;
+
+int dense_min_of(const fof_options &o) { return o.dense_min > 0 ? o.dense_min : kDefaultDenseMin; }
 
 fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box, const double *lx, int32_t n_boxes,
                      HostPlan *out)
@@ -196,6 +203,8 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.o_perm = take(sizeof(int32_t) * 2 * n);
     p.o_parent = take(sizeof(int32_t) * n);
     p.o_gsize = take(sizeof(int32_t) * n);
+    p.max_items = fof::max_dense_items(p.n, dense_min_of(c->opt));
+    p.o_items = take(sizeof(int32_t) * 4 * (size_t)p.max_items);
     p.total = o;
     *out = std::move(p);
     return FOF_OK;
@@ -223,7 +232,8 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     if (c->ws_bytes < np.total) return FOF_ERR_WORKSPACE;
     fof_status st = ensure_device(c);
     if (st != FOF_OK) return st;
-    const bool same = c->planned && c->uploaded && c->plan.same_geometry(np);
+    // a single box travels in the kernel arguments: nothing to upload
+    const bool same = np.n_boxes == 1 || (c->planned && c->uploaded && c->plan.same_geometry(np));
     if (!same) {
         const size_t table = np.o_counters;   // boxes + p0 region
         // the staging buffer may still feed an earlier, in-flight copy
@@ -254,6 +264,10 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.strict = c->opt.strict_less;
     d.stats = c->opt.collect_stats;
     d.scan_tiles = p.scan_tiles;
+    d.dense_min = dense_min_of(c->opt);
+    d.dense_blocks = kDenseBlocks;
+    d.max_items = p.max_items;
+    d.box0 = p.boxes[0];
     d.boxes = at<BoxDev>(c->ws, p.o_boxes);
     d.box_p0 = at<int64_t>(c->ws, p.o_p0);
     d.counters = at<Counters>(c->ws, p.o_counters);
@@ -265,6 +279,7 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.perm = at<int2>(c->ws, p.o_perm);
     d.parent = at<int32_t>(c->ws, p.o_parent);
     d.gsize = at<int32_t>(c->ws, p.o_gsize);
+    d.items = at<int4>(c->ws, p.o_items);
     return FOF_OK;
 }
 
@@ -354,7 +369,10 @@ fof_status fof_set_workspace(fof_ctx *ctx, void *d_ws, size_t bytes)
 {
     if (!ctx) return FOF_ERR_INVALID_ARG;
     if (d_ws && (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) return FOF_ERR_WORKSPACE;
-    if (ctx->ws != d_ws) ctx->uploaded = false;
+    if (ctx->ws != d_ws) {
+        ctx->uploaded = false;
+        ctx->planned = false;   // the carved pointers refer to the old workspace
+    }
     ctx->ws = d_ws;
     ctx->ws_bytes = d_ws ? bytes : 0;
     ctx->state = 0;
@@ -398,7 +416,7 @@ fof_status fof_finalize(fof_ctx *ctx, int32_t *d_group_index, int32_t *d_group_s
 fof_status fof_read_n_groups(fof_ctx *ctx, int64_t *h_n_groups)
 {
     if (!ctx || !h_n_groups) return FOF_ERR_INVALID_ARG;
-    if (!ctx->planned || !ctx->uploaded) return FOF_ERR_BAD_STATE;
+    if (!ctx->planned) return FOF_ERR_BAD_STATE;
     return read_back(ctx, h_n_groups, nullptr);
 }
 
@@ -406,7 +424,7 @@ fof_status fof_get_stats(fof_ctx *ctx, fof_stats *out)
 {
     if (!ctx || !out) return FOF_ERR_INVALID_ARG;
     std::memset(out, 0, sizeof(*out));
-    if (!ctx->planned || !ctx->uploaded) return FOF_ERR_BAD_STATE;
+    if (!ctx->planned) return FOF_ERR_BAD_STATE;
     std::vector<int64_t> g((size_t)ctx->plan.n_boxes);
     Counters cnt{};
     fof_status st = read_back(ctx, g.data(), &cnt);

@@ -1,0 +1,213 @@
+// Device helpers shared by the gfx950 kernels (build, link, finalize).
+#pragma once
+
+#include <climits>
+
+#include "fof_internal.h"
+
+namespace fof {
+namespace dev {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ int find_box(const int64_t *p0, int n_boxes, int64_t i)
+{
+    int lo = 0, hi = n_boxes - 1;   // last box whose first particle is <= i
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (p0[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Cell coordinate along one axis: floor(x * nc / L) clamped to [0, nc - 1].
+// The product is formed in double, so for L = 1 it is exact; a NaN lands in
+// cell 0 (the coordinate error is latched separately).
+__device__ __forceinline__ int cell_coord(float x, double inv_h, int nc)
+{
+    double t = (double)x * inv_h;
+    t = fmin(fmax(t, 0.0), (double)(nc - 1));
+    return (int)t;
+}
+
+__device__ __forceinline__ bool in_box(float x, double L)
+{
+    double d = (double)x;
+    return d >= 0.0 && d < L;  // false for NaN and infinities
+}
+
+// The link predicate, in double, exactly as the oracle states it: subtract,
+// wrap to the minimum image, square and sum left to right, no FMA.
+__device__ __forceinline__ bool link_fp64(float ax, float ay, float az, float bx, float by, float bz,
+                                          double L, double half, double l2, bool strict)
+{
+    double tx = (double)ax - (double)bx;
+    if (tx > half) tx = tx - L;
+    else if (tx < -half) tx = tx + L;
+    double ty = (double)ay - (double)by;
+    if (ty > half) ty = ty - L;
+    else if (ty < -half) ty = ty + L;
+    double tz = (double)az - (double)bz;
+    if (tz > half) tz = tz - L;
+    else if (tz < -half) tz = tz + L;
+    double sxy = tx * tx + ty * ty;
+    double r2 = sxy + tz * tz;
+    return strict ? (r2 < l2) : (r2 <= l2);
+}
+
+// ------------------------------------------------------------ union-find --
+// parent[] is read and written with device-scope relaxed atomics: the eight
+// XCDs have private L2 caches, and plain loads could keep returning a stale
+// line while other XCDs hook roots.
+
+__device__ __forceinline__ int ld_rel(const int *a)
+{
+    return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_rel(int *a, int v)
+{
+    __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x with path halving: each visited node is re-pointed to its
+// grandparent. The store may race with other finds; every value written is an
+// ancestor of the node with a smaller index, so the forest stays valid.
+__device__ __forceinline__ int find_halve(int *parent, int x)
+{
+    while (true) {
+        int px = ld_rel(parent + x);
+        if (px == x) return x;
+        int gx = ld_rel(parent + px);
+        if (gx == px) return px;
+        st_rel(parent + x, gx);
+        x = gx;
+    }
+}
+
+// Merge the groups of a and b: hook the larger root under the smaller with a
+// compare-and-swap that expects the larger root to still be a root. On failure
+// the CAS returns the node's new parent, and the search continues from there.
+__device__ __forceinline__ unsigned unite(int *parent, int a, int b)
+{
+    unsigned retries = 0;
+    while (true) {
+        a = find_halve(parent, a);
+        b = find_halve(parent, b);
+        if (a == b) return retries;
+        int lo = a < b ? a : b;
+        int hi = a < b ? b : a;
+        int expected = hi;
+        if (__hip_atomic_compare_exchange_strong(parent + hi, &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return retries;
+        ++retries;
+        a = expected;
+        b = lo;
+    }
+}
+
+// ------------------------------------------------------------ wave utils --
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = lane_id();
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over the block; `lds` holds one int per wave. Returns the
+// exclusive prefix of v and the block total in *total.
+template <int kThreads>
+__device__ __forceinline__ int block_excl_scan(int v, int *lds, int *total)
+{
+    constexpr int kWaves = kThreads / 64;
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    int inc = wave_incl_scan(v);
+    if (lane == 63) lds[wid] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        int s = lds[w];
+        off += (w < wid) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// Adds `v` into arr[key] with one atomic per distinct key among the active
+// lanes of the wave (key < 0: nothing to add). Every lane must call it.
+__device__ __forceinline__ void wave_add_by_key(int *arr, int key, int v)
+{
+    unsigned long long todo = __ballot(key >= 0);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int k = __shfl(key, leader, 64);
+        const bool mine = key == k;
+        int sum = mine ? v : 0;
+        for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
+        if (lane_id() == leader) atomicAdd(arr + k, sum);
+        todo &= ~__ballot(mine);
+    }
+}
+
+__device__ __forceinline__ void wave_add_by_key(unsigned long long *arr, int key, unsigned long long v)
+{
+    unsigned long long todo = __ballot(key >= 0);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int k = __shfl(key, leader, 64);
+        const bool mine = key == k;
+        unsigned long long sum = mine ? v : 0ull;
+        for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
+        if (lane_id() == leader) atomicAdd(arr + k, sum);
+        todo &= ~__ballot(mine);
+    }
+}
+
+// Atomic min of `v` into arr[key].y, one atomic per distinct key in the wave.
+__device__ __forceinline__ void wave_min_by_key(int2 *arr, int key, int v)
+{
+    unsigned long long todo = __ballot(key >= 0);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int k = __shfl(key, leader, 64);
+        const bool mine = key == k;
+        int m = mine ? v : INT_MAX;
+        for (int d = 32; d >= 1; d >>= 1) m = min(m, __shfl_xor(m, d, 64));
+        if (lane_id() == leader) atomicMin(&arr[k].y, m);
+        todo &= ~__ballot(mine);
+    }
+}
+
+__device__ __forceinline__ int particle_cell(const BoxDev &bd, float x, float y, float z)
+{
+    const int nc = bd.nc;
+    int cx = cell_coord(x, bd.inv_h, nc);
+    int cy = cell_coord(y, bd.inv_h, nc);
+    int cz = cell_coord(z, bd.inv_h, nc);
+    return (int)(bd.cell_base + ((int64_t)cz * nc + cy) * nc + cx);
+}
+
+__device__ __forceinline__ const BoxDev &box_of(const Plan &p, int b)
+{
+    return p.n_boxes == 1 ? p.box0 : p.boxes[b];
+}
+
+}  // namespace dev
+}  // namespace fof

@@ -29,7 +29,8 @@ struct Counters {
     unsigned long long band_hits;
     unsigned long long cas_retries;
     unsigned int error;         // bit 0: coordinate outside [0, L) or not finite
-    unsigned int pad[7];
+    unsigned int n_items;       // work items of the dense link kernel
+    unsigned int pad[6];
 };
 
 // Everything a launch needs: raw pointers into the caller's workspace.
@@ -41,18 +42,23 @@ struct Plan {
     int32_t strict;         // 1: r2 < l2
     int32_t stats;          // 1: count pair tests etc.
     int64_t scan_tiles;     // tiles of the cell-count scan
+    int32_t dense_min;      // cells with at least this many particles use the wave kernel
+    int32_t dense_blocks;   // grid of the persistent dense link kernel
+    int64_t max_items;      // capacity of `items`
 
+    BoxDev box0;            // the box itself when n_boxes == 1 (no table read)
     const float *pos;       // [n][3] input
-    const BoxDev *boxes;    // [n_boxes]
+    const BoxDev *boxes;    // [n_boxes] (read only when n_boxes > 1)
     const int64_t *box_p0;  // [n_boxes + 1] particle offsets
 
     int32_t *cell;          // [n_cells + 1] counts, then exclusive prefix (cell start)
     int32_t *scan_part;     // [scan_tiles] tile sums
-    int32_t *rank;          // [n] slot of particle i inside its cell
-    float4 *sorted;         // [n] cell-sorted x, y, z
+    int32_t *rank;          // [n] slot of particle i inside its cell; after the scatter its sorted slot
+    float4 *sorted;         // [n] cell-sorted x, y, z; after the link: {label, size} per sorted slot
     int2 *perm;             // [n] .x original index of sorted particle s, .y group minimum (at roots)
     int32_t *parent;        // [n] union-find forest over sorted indices
     int32_t *gsize;         // [n] group member count at roots (sorted indices)
+    int4 *items;            // [max_items] dense work: {cell, first home particle, box, 0}
     unsigned long long *n_groups;  // [n_boxes]
     Counters *counters;
 
@@ -63,7 +69,10 @@ struct Plan {
 // Tiles of the cell-count scan for n_cells cells (fof_kernels.hip).
 int64_t scan_tiles_for(int64_t n_cells);
 
-// Kernel launchers (fof_kernels.hip). All enqueue on `stream`.
+// Capacity of the dense work-item list (fof_link.hip).
+int64_t max_dense_items(int64_t n, int dense_min);
+
+// Kernel launchers (fof_kernels.hip, fof_link.hip). All enqueue on `stream`.
 hipError_t launch_clear(const Plan &p, hipStream_t stream);
 hipError_t launch_build(const Plan &p, hipStream_t stream);
 hipError_t launch_link(const Plan &p, hipStream_t stream);

@@ -20,8 +20,9 @@ pytestmark = pytest.mark.gpu
 PREDICATES = ["fp32_filter", "fp64"]
 
 
-def gpu_run(pos, offsets, box, lx, predicate="fp32_filter", strict=False, cell_factor=0.0, stats=False):
-    f = fof.FoF(predicate, strict, cell_factor, stats)
+def gpu_run(pos, offsets, box, lx, predicate="fp32_filter", strict=False, cell_factor=0.0, stats=False,
+            dense_min=0):
+    f = fof.FoF(predicate, strict, cell_factor, stats, dense_min=dense_min)
     try:
         p = torch.from_numpy(np.ascontiguousarray(pos, dtype=np.float32)).cuda()
         label, size, ng = f.run(p, offsets, box, lx)
@@ -31,9 +32,9 @@ def gpu_run(pos, offsets, box, lx, predicate="fp32_filter", strict=False, cell_f
         f.close()
 
 
-def assert_single(pos, lx, box=1.0, strict=False, predicate="fp32_filter", cell_factor=0.0):
+def assert_single(pos, lx, box=1.0, strict=False, predicate="fp32_filter", cell_factor=0.0, dense_min=0):
     ref = oracle.fof(pos, lx, box, strict=strict)
-    lab, size, ng, _ = gpu_run(pos, [0, len(pos)], box, lx, predicate, strict, cell_factor)
+    lab, size, ng, _ = gpu_run(pos, [0, len(pos)], box, lx, predicate, strict, cell_factor, dense_min=dense_min)
     assert np.array_equal(lab, ref[0])
     assert np.array_equal(size, ref[1])
     assert int(ng[0]) == ref[2]
@@ -139,6 +140,38 @@ def test_cell_sizes(cell_factor):
     lx = synth.linking_length(0.2, n)
     for predicate in PREDICATES:
         assert_single(pos, lx, predicate=predicate, cell_factor=cell_factor)
+
+
+# dense_min = 1: every non-empty cell is searched by whole wavefronts;
+# dense_min = 1 << 30: every cell per lane; between: both kernels meet.
+@pytest.mark.parametrize("dense_min", [1, 2, 8, 64, 100, 1 << 30])
+@pytest.mark.parametrize("predicate", PREDICATES)
+def test_dense_and_sparse_kernels(dense_min, predicate):
+    n = 120000
+    pos = synth.clustered(n, 17, 0, 0.7)
+    for b, cf in ((0.2, 0.0), (0.5, 1.0), (0.3, 2.5)):
+        assert_single(pos, synth.linking_length(b, n), predicate=predicate, cell_factor=cf, dense_min=dense_min)
+
+
+@pytest.mark.parametrize("dense_min", [1, 1 << 30])
+def test_kernel_paths_on_hand_cases(dense_min):
+    fx = load_fixture("fig2_indirect_u.txt")
+    for strict, tag in ((False, "le"), (True, "lt")):
+        for predicate in PREDICATES:
+            lab, size, ng, _ = gpu_run(fx["pos"], [0, len(fx["pos"])], fx["box"], fx["lx"], predicate, strict,
+                                       dense_min=dense_min)
+            assert np.array_equal(lab, fx["labels_" + tag]) and np.array_equal(size, fx["sizes_" + tag])
+    pos = lattice(16, seed=5)
+    for predicate in PREDICATES:
+        lab, size, ng, _ = gpu_run(pos, [0, len(pos)], 1.0, (1 + 1e-3) / 16, predicate, dense_min=dense_min)
+        assert int(ng[0]) == 1
+    for axis in range(3):
+        assert_single(chain_across_boundary(40, 0.0234375, axis), 0.03125, dense_min=dense_min)
+    w = synth.make("batched256", n_boxes=12, size_scale=0.05)
+    ref = oracle.fof_boxes(w.pos, w.offsets, w.box, w.lx)
+    for predicate in PREDICATES:
+        lab, size, ng, _ = gpu_run(w.pos, w.offsets, w.box, w.lx, predicate, dense_min=dense_min)
+        assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and np.array_equal(ng, ref[2])
 
 
 def test_uniform32k_and_strict():
