@@ -91,7 +91,10 @@ typedef struct {
     int64_t band_hits;       /* FP32 results inside the band  (collect_stats only) */
     int64_t cas_retries;     /* failed compare-and-swaps      (collect_stats only) */
     int64_t fp64_boxes;      /* boxes the FP32 filter could not serve (decided in double) */
-    int64_t reserved[8];
+    int64_t sparse_pair_tests; /* of pair_tests, those made by the per-particle search (collect_stats only) */
+    int64_t queued_links;    /* linked pairs queued for the deferred union pass */
+    int64_t dense_items;     /* wavefront work items (64 particles of a dense cell each) */
+    int64_t reserved[5];
 } fof_stats;
 
 /* Fills *opt with the defaults: FP32 filter, r2 <= l2, automatic cells, no stats. */

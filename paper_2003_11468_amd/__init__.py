@@ -43,7 +43,9 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("n_particles", ctypes.c_int64), ("n_cells", ctypes.c_int64), ("n_groups", ctypes.c_int64),
                 ("pair_tests", ctypes.c_int64), ("links", ctypes.c_int64), ("band_hits", ctypes.c_int64),
-                ("cas_retries", ctypes.c_int64), ("fp64_boxes", ctypes.c_int64), ("reserved", ctypes.c_int64 * 8)]
+                ("cas_retries", ctypes.c_int64), ("fp64_boxes", ctypes.c_int64),
+                ("sparse_pair_tests", ctypes.c_int64), ("queued_links", ctypes.c_int64),
+                ("dense_items", ctypes.c_int64), ("reserved", ctypes.c_int64 * 5)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -49,7 +49,8 @@ struct HostPlan {
     std::vector<int64_t> p0;
     // workspace layout (byte offsets)
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_rank = 0, o_sorted = 0,
-           o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, total = 0;
+           o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, total = 0;
+    int64_t max_edges = 0;
 
     bool same_geometry(const HostPlan &o) const
     {
@@ -145,6 +146,7 @@ void fp32_thresholds(BoxDev &b, double lx)
 
 constexpr int kDefaultDenseMin = 32;
 constexpr int kDenseBlocks = 2048;
+constexpr int kSparseBlocks = 1024;
 
 int dense_min_of(const fof_options &o) { return o.dense_min > 0 ? o.dense_min : kDefaultDenseMin; }
 
@@ -205,6 +207,10 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.o_gsize = take(sizeof(int32_t) * n);
     p.max_items = fof::max_dense_items(p.n, dense_min_of(c->opt));
     p.o_items = take(sizeof(int32_t) * 4 * (size_t)p.max_items);
+    // linked pairs of sparse cells, merged after the search; a pair that finds
+    // the list full is merged on the spot instead
+    p.max_edges = p.n > (1 << 20) ? p.n : (1 << 20);
+    p.o_edges = take(sizeof(int32_t) * 2 * (size_t)p.max_edges);
     p.total = o;
     *out = std::move(p);
     return FOF_OK;
@@ -266,7 +272,9 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.scan_tiles = p.scan_tiles;
     d.dense_min = dense_min_of(c->opt);
     d.dense_blocks = kDenseBlocks;
+    d.sparse_blocks = kSparseBlocks;
     d.max_items = p.max_items;
+    d.max_edges = p.max_edges;
     d.box0 = p.boxes[0];
     d.boxes = at<BoxDev>(c->ws, p.o_boxes);
     d.box_p0 = at<int64_t>(c->ws, p.o_p0);
@@ -280,6 +288,7 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.parent = at<int32_t>(c->ws, p.o_parent);
     d.gsize = at<int32_t>(c->ws, p.o_gsize);
     d.items = at<int4>(c->ws, p.o_items);
+    d.edges = at<int2>(c->ws, p.o_edges);
     return FOF_OK;
 }
 
@@ -436,6 +445,9 @@ fof_status fof_get_stats(fof_ctx *ctx, fof_stats *out)
     out->band_hits = (int64_t)cnt.band_hits;
     out->cas_retries = (int64_t)cnt.cas_retries;
     out->fp64_boxes = ctx->plan.fp64_boxes;
+    out->sparse_pair_tests = (int64_t)cnt.sparse_tests;
+    out->queued_links = (int64_t)cnt.n_edges;
+    out->dense_items = (int64_t)cnt.n_items;
     return st;
 }
 

@@ -28,9 +28,11 @@ struct Counters {
     unsigned long long links;
     unsigned long long band_hits;
     unsigned long long cas_retries;
+    unsigned long long sparse_tests;   // pair tests of the per-lane (sparse) search
     unsigned int error;         // bit 0: coordinate outside [0, L) or not finite
     unsigned int n_items;       // work items of the dense link kernel
-    unsigned int pad[6];
+    unsigned int n_edges;       // linked pairs queued for the union kernel (may exceed capacity)
+    unsigned int pad[5];
 };
 
 // Everything a launch needs: raw pointers into the caller's workspace.
@@ -44,7 +46,9 @@ struct Plan {
     int64_t scan_tiles;     // tiles of the cell-count scan
     int32_t dense_min;      // cells with at least this many particles use the wave kernel
     int32_t dense_blocks;   // grid of the persistent dense link kernel
+    int32_t sparse_blocks;  // grid of the persistent sparse link kernel
     int64_t max_items;      // capacity of `items`
+    int64_t max_edges;      // capacity of `edges`
 
     BoxDev box0;            // the box itself when n_boxes == 1 (no table read)
     const float *pos;       // [n][3] input
@@ -59,6 +63,7 @@ struct Plan {
     int32_t *parent;        // [n] union-find forest over sorted indices
     int32_t *gsize;         // [n] group member count at roots (sorted indices)
     int4 *items;            // [max_items] dense work: {cell, first home particle, box, 0}
+    int2 *edges;            // [max_edges] linked pairs found by the sparse search
     unsigned long long *n_groups;  // [n_boxes]
     Counters *counters;
 

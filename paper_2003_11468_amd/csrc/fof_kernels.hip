@@ -42,8 +42,10 @@ __global__ void __launch_bounds__(kBlock) k_clear(Plan p)
         p.counters->links = 0;
         p.counters->band_hits = 0;
         p.counters->cas_retries = 0;
+        p.counters->sparse_tests = 0;
         p.counters->error = 0;
         p.counters->n_items = 0;
+        p.counters->n_edges = 0;
     }
 }
 

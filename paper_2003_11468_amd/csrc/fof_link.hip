@@ -63,140 +63,322 @@ __device__ __forceinline__ int unite_root(int *parent, int a, int b, unsigned &r
 
 // --------------------------------------------------------- sparse (lane) --
 
-// Particle s against the sorted particles [j0, j1). hx/hy/hz: home coordinates
-// (minus L on axes where the home cell is the top one); sx/sy/sz: L on axes
-// where the neighbour cell is the top one reached through the boundary.
-template <bool kFP64, bool kStats>
-__device__ __forceinline__ void lane_range(const Plan &p, const BoxDev &bd, int s, float4 pi, int j0, int j1,
-                                           float hx, float hy, float hz, float sx, float sy, float sz, double Lx,
-                                           double Ly, double Lz, int &root, unsigned long long &tests,
-                                           unsigned long long &links, unsigned long long &band, unsigned &retries)
+// Periodic shift code of one axis for a candidate range: 0 none; 1 the
+// neighbour cell is the top one reached across the low face (candidate - L is
+// exact); 2 the home cell is the top one and the neighbour lies across the
+// high face (home - L is exact). Codes of x, y, z sit in bits 0-1, 2-3, 4-5.
+__device__ __forceinline__ float axis_diff(float h, float q, int code, float L32)
 {
-    const bool strict = p.strict != 0;
-    for (int j = j0; j < j1; ++j) {
-        const float4 pj = p.sorted[j];
-        bool link;
-        if constexpr (kFP64) {
-            double tx = ((double)pi.x - (double)pj.x) + Lx;
-            double ty = ((double)pi.y - (double)pj.y) + Ly;
-            double tz = ((double)pi.z - (double)pj.z) + Lz;
-            double sxy = tx * tx + ty * ty;
-            double r2 = sxy + tz * tz;
-            link = strict ? (r2 < bd.l2) : (r2 <= bd.l2);
-        } else {
-            const float dx = hx - (pj.x - sx);
-            const float dy = hy - (pj.y - sy);
-            const float dz = hz - (pj.z - sz);
-            const float r = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            if (r < bd.lo32) link = true;
-            else if (r > bd.hi32) link = false;
-            else {
-                if (kStats) ++band;
-                link = link_fp64(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, bd.L, bd.half, bd.l2, strict);
+    const float hh = code == 2 ? h - L32 : h;
+    const float qq = code == 1 ? q - L32 : q;
+    return hh - qq;
+}
+
+__device__ __forceinline__ double axis_shift(int code, double L) { return code == 1 ? L : (code == 2 ? -L : 0.0); }
+
+constexpr int kMaxRanges = 10;
+
+struct Ranges {
+    int j0[kMaxRanges], j1[kMaxRanges], code[kMaxRanges];
+    int n = 0;
+    __device__ __forceinline__ void add(int a, int b, int c)
+    {
+        if (b <= a) return;
+#pragma unroll
+        for (int r = 0; r < kMaxRanges; ++r)
+            if (r == n) {
+                j0[r] = a;
+                j1[r] = b;
+                code[r] = c;
+            }
+        ++n;
+    }
+};
+
+// The three cells (x = cx-1, cx, cx+1) of one neighbour row, given their
+// boundaries b0..b3 (b_e = start of cell e, b_{e+1} its end when the cells
+// are contiguous) and whether the row wraps at either end. Runs of sparse,
+// memory-contiguous cells are merged into one range: at most two per row.
+__device__ __forceinline__ void add_row(Ranges &R, const int st[3], const int en[3], const int xcode[3],
+                                        int yz_code, int dense_min)
+{
+    int a = -1, b = -1, code = 0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const bool sparse = en[e] - st[e] < dense_min;
+        const int c = xcode[e] | yz_code;
+        if (sparse && en[e] > st[e]) {
+            if (a >= 0 && st[e] == b && c == code) {
+                b = en[e];
+            } else {
+                if (a >= 0) R.add(a, b, code);
+                a = st[e];
+                b = en[e];
+                code = c;
             }
         }
-        if (kStats) ++tests;
-        if (link) {
-            if (kStats) ++links;
-            root = unite_root(p.parent, root, j, retries);
-        }
     }
+    if (a >= 0) R.add(a, b, code);
 }
+
+// Linked pairs of the sparse search are not merged where they are found: a
+// union is a chain of dependent memory accesses, and inside the search it
+// would stall the whole wavefront round after round. Each wave collects its
+// pairs in LDS and appends them to a global edge list 64 at a time; the
+// union kernel then merges all of them with one thread per pair.
+constexpr int kEdgeBuf = 128;
+
+struct EdgeSink {
+    int2 *buf;      // this wave's LDS buffer [kEdgeBuf]
+    int count;      // wave-uniform fill level
+
+    // Appends (s, j) for every lane with `has`; flushes once 64 are waiting.
+    __device__ __forceinline__ void push(const Plan &p, bool has, int s, int j, unsigned &retries)
+    {
+        const unsigned long long m = __ballot(has);
+        if (!m) return;
+        if (has) {
+            const int at = count + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            buf[at] = make_int2(s, j);
+        }
+        count += __popcll(m);
+        __builtin_amdgcn_wave_barrier();
+        if (count >= 64) flush(p, retries);
+    }
+
+    __device__ __forceinline__ void flush(const Plan &p, unsigned &retries)
+    {
+        if (count == 0) return;
+        const int lane = lane_id();
+        unsigned base = 0;
+        if (lane == 0) base = atomicAdd(&p.counters->n_edges, (unsigned)count);
+        base = (unsigned)__shfl((int)base, 0, 64);
+        for (int k = lane; k < count; k += 64) {
+            const int2 e = buf[k];
+            const unsigned at = base + (unsigned)k;
+            if ((int64_t)at < p.max_edges) p.edges[at] = e;
+            else retries += unite(p.parent, e.x, e.y);   // list full: merge here
+        }
+        __builtin_amdgcn_wave_barrier();
+        count = 0;
+    }
+};
+
+// Per-wave LDS for the sparse search: the candidate ranges ("units") of the
+// wave's 64 home particles, flattened into one list of pairs by a prefix sum,
+// so that every lane tests a pair in every step whatever the range lengths.
+constexpr int kMaxUnits = 64 * kMaxRanges;
+
+struct SparseLds {
+    int start[kMaxUnits + 1];   // first pair of each unit (exclusive prefix)
+    int j0[kMaxUnits];          // first candidate of each unit
+    int tag[kMaxUnits];         // shift code (bits 0-5) | home lane << 8
+    float4 home[64];            // the home particles
+    int2 ebuf[kEdgeBuf];        // edge sink buffer
+};
 
 template <bool kFP64, bool kStats>
 __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
 {
-    const int64_t s64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    __shared__ SparseLds lds[kWaves];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    SparseLds &L = lds[wid];
+    EdgeSink sink{L.ebuf, 0};
     unsigned long long tests = 0, links = 0, band = 0;
     unsigned retries = 0;
-    if (s64 < p.n) {
-        const int s = (int)s64;
-        const int b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, s64);
-        const BoxDev &bd = box_of(p, b);
-        const float4 pi = p.sorted[s];
-        const int nc = bd.nc;
-        const int cx = cell_coord(pi.x, bd.inv_h, nc);
-        const int cy = cell_coord(pi.y, bd.inv_h, nc);
-        const int cz = cell_coord(pi.z, bd.inv_h, nc);
-        const int cb = (int)bd.cell_base;
-        const int c = cb + (cz * nc + cy) * nc + cx;
-        const int *cell = p.cell;
-        const int dense_min = p.dense_min;
-        // The 13 half-shell cells lie in 5 rows of x-consecutive cells: the own
-        // row (cell cx + 1) and the rows (dy, dz) = (1, 0), (-1, 1), (0, 1),
-        // (1, 1) (cells cx - 1, cx, cx + 1). Away from the x faces one 16-byte
-        // load per row returns the four boundaries of its three cells; all
-        // rows are requested before any candidate is read.
-        int j0[13], j1[13];
-        const int own_start = cell[c];
-        const int own_end = cell[c + 1];
-        const bool inner = cx >= 1 && cx + 1 < nc;   // boundaries cx-1 .. cx+2 lie in the row (cx+2 may be the next row's start = end of this row)
-        {
-            const int nxp = cx + 1 < nc ? cx + 1 : 0;
+    const int64_t n_tiles = (p.n + 63) / 64;
+    for (int64_t tile = (int64_t)blockIdx.x * kWaves + wid; tile < n_tiles; tile += (int64_t)gridDim.x * kWaves) {
+        const int64_t s64 = tile * 64 + lane;
+        Ranges R;
+        float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+        int b = 0;
+        if (s64 < p.n) {
+            const int s = (int)s64;
+            b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, s64);
+            const BoxDev &bd = box_of(p, b);
+            pi = p.sorted[s];
+            const int nc = bd.nc;
+            const int cx = cell_coord(pi.x, bd.inv_h, nc);
+            const int cy = cell_coord(pi.y, bd.inv_h, nc);
+            const int cz = cell_coord(pi.z, bd.inv_h, nc);
+            const int cb = (int)bd.cell_base;
+            const int c = cb + (cz * nc + cy) * nc + cx;
+            const int *cell = p.cell;
+            const int dense_min = p.dense_min;
             const int rb0 = c - cx;
-            j0[0] = cell[rb0 + nxp];
-            j1[0] = cell[rb0 + nxp + 1];
-        }
-        const int rdy[4] = {1, -1, 0, 1}, rdz[4] = {0, 1, 1, 1};
+            // Boundaries of the own row and the four neighbour rows (dy, dz) =
+            // (1, 0), (-1, 1), (0, 1), (1, 1): with the own cell these hold the
+            // 13 half-shell cells. All are requested before any is used.
+            const int own_start = cell[c], own_end = cell[c + 1];
+            const int nxp = cx + 1 < nc ? cx + 1 : 0;
+            const int nxt_start = cell[rb0 + nxp], nxt_end = cell[rb0 + nxp + 1];
+            const bool inner = cx >= 1 && cx + 1 < nc;
+            const int rdy[4] = {1, -1, 0, 1}, rdz[4] = {0, 1, 1, 1};
+            int st[4][3], en[4][3], yz[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int ny = cy + rdy[r], nz = cz + rdz[r];
-            ny += ny < 0 ? nc : (ny >= nc ? -nc : 0);
-            nz += nz >= nc ? -nc : 0;
-            const int rb = cb + (nz * nc + ny) * nc;
-            if (inner) {
-                typedef int int4a4 __attribute__((ext_vector_type(4), aligned(4)));
-                const int4a4 q = *reinterpret_cast<const int4a4 *>(cell + rb + cx - 1);
-                j0[1 + 3 * r] = q.x; j1[1 + 3 * r] = q.y;
-                j0[2 + 3 * r] = q.y; j1[2 + 3 * r] = q.z;
-                j0[3 + 3 * r] = q.z; j1[3 + 3 * r] = q.w;
-            } else {
+            for (int r = 0; r < 4; ++r) {
+                int ny = cy + rdy[r], nz = cz + rdz[r], code = 0;
+                if (ny >= nc) { ny -= nc; code |= 2 << 2; }
+                else if (ny < 0) { ny += nc; code |= 1 << 2; }
+                if (nz >= nc) { nz -= nc; code |= 2 << 4; }
+                yz[r] = code;
+                const int rb = cb + (nz * nc + ny) * nc;
+                if (inner) {
+                    typedef int int4a4 __attribute__((ext_vector_type(4), aligned(4)));
+                    const int4a4 q = *reinterpret_cast<const int4a4 *>(cell + rb + cx - 1);
+                    st[r][0] = q.x; en[r][0] = q.y;
+                    st[r][1] = q.y; en[r][1] = q.z;
+                    st[r][2] = q.z; en[r][2] = q.w;
+                } else {
 #pragma unroll
-                for (int e = 0; e < 3; ++e) {
-                    int nx = cx - 1 + e;
-                    nx += nx < 0 ? nc : (nx >= nc ? -nc : 0);
-                    j0[1 + 3 * r + e] = cell[rb + nx];
-                    j1[1 + 3 * r + e] = cell[rb + nx + 1];
+                    for (int e = 0; e < 3; ++e) {
+                        int nx = cx - 1 + e;
+                        nx += nx < 0 ? nc : (nx >= nc ? -nc : 0);
+                        st[r][e] = cell[rb + nx];
+                        en[r][e] = cell[rb + nx + 1];
+                    }
                 }
             }
-        }
-        // neighbour k: offset (dx, dy, dz) of slot k in the table above
-        const int kdx[13] = {1, -1, 0, 1, -1, 0, 1, -1, 0, 1, -1, 0, 1};
-        const int kdy[13] = {0, 1, 1, 1, -1, -1, -1, 0, 0, 0, 1, 1, 1};
-        const int kdz[13] = {0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1};
-        if (own_end - own_start < dense_min) {
-            const float L32 = bd.L32;
-            const double L = bd.L;
-            int root = s;
-            lane_range<kFP64, kStats>(p, bd, s, pi, s + 1, own_end, pi.x, pi.y, pi.z, 0.f, 0.f, 0.f, 0.0, 0.0, 0.0,
-                                      root, tests, links, band, retries);
-#pragma unroll 1
-            for (int k = 0; k < 13; ++k) {
-                if (j1[k] - j0[k] >= dense_min || j1[k] == j0[k]) continue;   // dense: that cell searches the pair
-                const int dx = kdx[k], dy = kdy[k], dz = kdz[k];
-                float hx = pi.x, hy = pi.y, hz = pi.z, sx = 0.f, sy = 0.f, sz = 0.f;
-                double Lx = 0.0, Ly = 0.0, Lz = 0.0;
-                if (cx + dx < 0) { sx = L32; Lx = L; }
-                else if (cx + dx >= nc) { hx = pi.x - L32; Lx = -L; }
-                if (cy + dy < 0) { sy = L32; Ly = L; }
-                else if (cy + dy >= nc) { hy = pi.y - L32; Ly = -L; }
-                if (cz + dz >= nc) { hz = pi.z - L32; Lz = -L; }
-                lane_range<kFP64, kStats>(p, bd, s, pi, j0[k], j1[k], hx, hy, hz, sx, sy, sz, Lx, Ly, Lz, root,
-                                          tests, links, band, retries);
+            if (own_end - own_start < dense_min) {
+                // own cell above s, then cell cx + 1 (across the high x face when cx is the top cell)
+                const int xcode_next = cx + 1 < nc ? 0 : 2;
+                if (nxt_end - nxt_start < dense_min && xcode_next == 0 && nxt_start == own_end) {
+                    R.add(s + 1, nxt_end, 0);
+                } else {
+                    R.add(s + 1, own_end, 0);
+                    if (nxt_end - nxt_start < dense_min) R.add(nxt_start, nxt_end, xcode_next);
+                }
+                const int xcode[3] = {cx == 0 ? 1 : 0, 0, cx + 1 == nc ? 2 : 0};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) add_row(R, st[r], en[r], xcode, yz[r], dense_min);
             }
         }
+        // flatten the units of the wave: unit and pair offsets by prefix sums
+        int my_pairs = 0;
+#pragma unroll
+        for (int r = 0; r < kMaxRanges; ++r)
+            if (r < R.n) my_pairs += R.j1[r] - R.j0[r];
+        const int unit_incl = wave_incl_scan(R.n);
+        const int pair_incl = wave_incl_scan(my_pairs);
+        const int n_units = __shfl(unit_incl, 63, 64);
+        const int n_pairs = __shfl(pair_incl, 63, 64);
+        if (n_pairs == 0) continue;
+        {
+            int u = unit_incl - R.n, pr = pair_incl - my_pairs;
+#pragma unroll
+            for (int r = 0; r < kMaxRanges; ++r)
+                if (r < R.n) {
+                    L.start[u] = pr;
+                    L.j0[u] = R.j0[r];
+                    L.tag[u] = R.code[r] | (lane << 8);
+                    pr += R.j1[r] - R.j0[r];
+                    ++u;
+                }
+            if (lane == 63) L.start[n_units] = n_pairs;
+            L.home[lane] = pi;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // a tile inside one box uses that box's parameters for every pair;
+        // otherwise each pair reads the box of its home particle
+        const int b0 = __builtin_amdgcn_readfirstlane(b);
+        const bool one_box = __ballot(b != b0) == 0;
+        const bool strict = p.strict != 0;
+        // Each step takes kLanePairs pairs per lane (consecutive chunks of 64),
+        // so their unit searches and candidate loads overlap.
+        constexpr int kLanePairs = 4;
+        for (int base = 0; base < n_pairs; base += 64 * kLanePairs) {
+            int unit[kLanePairs];
+#pragma unroll
+            for (int k = 0; k < kLanePairs; ++k) {
+                const int q = base + 64 * k + lane;
+                int lo = 0;   // last unit with start <= q: fixed-depth search over at most 640 units
+#pragma unroll
+                for (int step = 512; step > 0; step >>= 1) {
+                    const int nxt = lo + step;
+                    if (nxt < n_units && L.start[nxt] <= q) lo = nxt;
+                }
+                unit[k] = lo;
+            }
+            float4 cand[kLanePairs];
+            int jj[kLanePairs], tg[kLanePairs];
+#pragma unroll
+            for (int k = 0; k < kLanePairs; ++k) {
+                const int q = base + 64 * k + lane;
+                tg[k] = L.tag[unit[k]];
+                jj[k] = L.j0[unit[k]] + (q - L.start[unit[k]]);
+                if (q < n_pairs) cand[k] = p.sorted[jj[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < kLanePairs; ++k) {
+                const int q = base + 64 * k + lane;
+                const bool live = q < n_pairs;
+                const int hl = tg[k] >> 8, code = tg[k] & 63;
+                const int j = jj[k];
+                const float4 h = L.home[hl];
+                const float4 c = cand[k];
+                const int s = (int)(tile * 64) + hl;
+                const int bq = one_box ? b0 : __shfl(b, hl, 64);   // all lanes take part in the shuffle
+                bool link = false;
+                if (live) {
+                    const BoxDev &bd = box_of(p, bq);
+                    if constexpr (kFP64) {
+                        const double tx = ((double)h.x - (double)c.x) + axis_shift(code & 3, bd.L);
+                        const double ty = ((double)h.y - (double)c.y) + axis_shift((code >> 2) & 3, bd.L);
+                        const double tz = ((double)h.z - (double)c.z) + axis_shift((code >> 4) & 3, bd.L);
+                        const double sxy = tx * tx + ty * ty;
+                        const double r2 = sxy + tz * tz;
+                        link = strict ? (r2 < bd.l2) : (r2 <= bd.l2);
+                    } else {
+                        const float dx = axis_diff(h.x, c.x, code & 3, bd.L32);
+                        const float dy = axis_diff(h.y, c.y, (code >> 2) & 3, bd.L32);
+                        const float dz = axis_diff(h.z, c.z, (code >> 4) & 3, bd.L32);
+                        const float rr = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                        if (rr < bd.lo32) link = true;
+                        else if (rr > bd.hi32) link = false;
+                        else {
+                            if (kStats) ++band;
+                            link = link_fp64(h.x, h.y, h.z, c.x, c.y, c.z, bd.L, bd.half, bd.l2, strict);
+                        }
+                    }
+                    if (kStats) ++tests;
+                    if (kStats && link) ++links;
+                }
+                sink.push(p, link, s, j, retries);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
+    sink.flush(p, retries);
     if (kStats) {
         tests = wave_sum_u64(tests);
         links = wave_sum_u64(links);
         band = wave_sum_u64(band);
         unsigned long long r = wave_sum_u64((unsigned long long)retries);
-        if (lane_id() == 0) {
+        if (lane == 0) {
+            atomicAdd(&p.counters->sparse_tests, tests);
             atomicAdd(&p.counters->pair_tests, tests);
             atomicAdd(&p.counters->links, links);
             atomicAdd(&p.counters->band_hits, band);
             atomicAdd(&p.counters->cas_retries, r);
         }
+    }
+}
+
+// Merges the queued pairs: one thread per pair, no ordering needed.
+template <bool kStats>
+__global__ void __launch_bounds__(kBlock) k_union_edges(Plan p)
+{
+    const unsigned n_edges = p.counters->n_edges;
+    const int64_t ne = (int64_t)n_edges < p.max_edges ? (int64_t)n_edges : p.max_edges;
+    unsigned retries = 0;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < ne; k += (int64_t)gridDim.x * kBlock) {
+        const int2 e = p.edges[k];
+        retries += unite(p.parent, e.x, e.y);
+    }
+    if (kStats) {
+        unsigned long long r = wave_sum_u64((unsigned long long)retries);
+        if (lane_id() == 0 && r) atomicAdd(&p.counters->cas_retries, r);
     }
 }
 
@@ -425,7 +607,8 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 template <bool kFP64, bool kStats>
 void launch_link_t(const Plan &p, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_link_sparse<kFP64, kStats>), dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p);
+    hipLaunchKernelGGL((k_link_sparse<kFP64, kStats>), dim3((unsigned)p.sparse_blocks), dim3(kBlock), 0, stream, p);
+    hipLaunchKernelGGL((k_union_edges<kStats>), dim3(4096), dim3(kBlock), 0, stream, p);
     hipLaunchKernelGGL((k_link_dense<kFP64, kStats>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
 }
 
