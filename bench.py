@@ -5,8 +5,11 @@ Workload (default): ``clustered256`` -- N = 256^3 FP32 positions in a periodic
 unit box, 60 % in Plummer halos (counts ~ M^-1.9 on [20, 1e5]), 40 % uniform,
 l_x = 0.2 x mean separation. One step = fof_build_cells + fof_link +
 fof_finalize over the whole input, positions already in HBM, labels and sizes
-left in HBM. The batched form (256 boxes of log-uniform size, one HIP graph)
-and the plain FP64 path are timed beside it and reported in the same line.
+left in HBM. Cell size and dense-cell threshold are autotuned beforehand
+(untimed) for each path. The batched form (256 boxes of log-uniform size in
+one HIP graph) and the plain FP64 path are timed beside it and reported in
+the same JSON line, with per-kernel device times from HIP events recorded on
+the launch stream inside the timed region.
 
 Prints one JSON line. ``--gpus`` above 1 is refused: this build runs on one GPU.
 """
@@ -25,11 +28,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "particles/s FoF labelled on 1 MI355X: FP32-filter+batched vs plain FP64, exact"
-FP32_VALU_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
+# Peaks: FP32 vector without packed math = 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz;
+# HBM3E 8 TB/s (vendor figures).
+FP32_VALU_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
-FLOP_PER_PAIR_TEST = 8            # 3 sub, 3 mul, 2 add (FMA counted as mul + add)
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2003_11468_amd", "csrc", "fof_kernels.hip")
+FLOP_PER_PAIR_TEST = 8            # 3 sub, 3 mul, 2 add (an FMA counts as mul + add)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2003_11468_amd", "csrc", f)
+                  for f in ("fof_kernels.hip", "fof_link.hip", "fof_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def algorithmic_bytes(kernel: str, n: int, cells: int, nonroot: int, edges: int):
+    """Bytes each HBM-bound pass must move at minimum (reads + writes)."""
+    table = {
+        "k_clear": 4 * cells,
+        "k_count": n * (12 + 8 + 12),            # xyz in; cell count RMW; slot, parent, size out
+        "k_scan_reduce": 4 * cells,
+        "k_scan_apply": 8 * cells,
+        "k_scatter": n * (12 + 4 + 4 + 16 + 8 + 4),  # xyz, slot, cell start in; sorted xyz, perm, slot map out
+        "k_union_edges": 8 * edges,
+        "k_flatten": 4 * n + nonroot * (4 + 4 + 8),  # parent in; root out, perm in, two atomics per non-root
+        "k_resolve": n * (4 + 8 + 8),            # parent, perm in; label+size per slot out
+        "k_gather": n * (4 + 8 + 8),             # slot map, label+size in; label, size out
+    }
+    return table.get(kernel)
 
 
 def log(msg: str):
@@ -42,61 +64,30 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clustered256")
-    ap.add_argument("--cell-factor", type=float, default=0.0)
+    ap.add_argument("--cell-factor", type=float, default=None, help="skip tuning, use this cell size")
+    ap.add_argument("--dense-min", type=int, default=None, help="skip tuning, use this dense threshold")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     return ap.parse_args()
 
 
-class Timer:
-    """HIP events on the stream the kernels are launched on."""
-
-    def __init__(self, torch, stream):
-        self.torch, self.stream = torch, stream
-
-    def event(self):
-        e = self.torch.cuda.Event(enable_timing=True)
-        e.record(self.stream)
-        return e
-
-
-def time_pipeline(torch, fof, f, pos, w, steps, warmup, label, size):
-    """Runs warmup + steps full passes; returns total ms and per-phase ms lists."""
-    t = Timer(torch, f.stream)
-    f.reserve(w.offsets, w.box, w.lx)
-    for _ in range(warmup):
-        fof.fof_build_cells(f.ctx, pos, w.offsets, w.box, w.lx)
-        fof.fof_link(f.ctx)
-        fof.fof_finalize(f.ctx, label, size)
-    torch.cuda.synchronize()
-    phases = []
-    start = t.event()
-    for _ in range(steps):
-        e0 = t.event()
-        fof.fof_build_cells(f.ctx, pos, w.offsets, w.box, w.lx)
-        e1 = t.event()
-        fof.fof_link(f.ctx)
-        e2 = t.event()
-        fof.fof_finalize(f.ctx, label, size)
-        e3 = t.event()
-        phases.append((e0, e1, e2, e3))
-    end = t.event()
-    torch.cuda.synchronize()
-    total = start.elapsed_time(end)
-    build = [a.elapsed_time(b) for a, b, _, _ in phases]
-    link = [b.elapsed_time(c) for _, b, c, _ in phases]
-    fin = [c.elapsed_time(d) for _, _, c, d in phases]
-    return total, build, link, fin
+def event(torch, stream):
+    e = torch.cuda.Event(enable_timing=True)
+    e.record(stream)
+    return e
 
 
 def source_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current kernel source."""
+    taken on the current kernel sources (else None)."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -105,6 +96,34 @@ def measured_traffic(kernel: str):
         return None
     k = d.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def choose(torch, tune, pos, w, predicate, args):
+    if args.cell_factor is not None and args.dense_min is not None:
+        return {"cell_factor": args.cell_factor, "dense_min": args.dense_min, "tuned": False}
+    t0 = time.perf_counter()
+    r = tune.autotune(pos, w.offsets, w.box, w.lx, predicate, cache_path=None, repeats=2)
+    return {"cell_factor": r["cell_factor"], "dense_min": r["dense_min"], "tuned": True,
+            "tuning_s": round(time.perf_counter() - t0, 2), "tried": r["tried"]}
+
+
+def timed_steps(torch, fof, f, pos, w, steps, warmup, label, size):
+    f.reserve(w.offsets, w.box, w.lx)
+    for _ in range(warmup):
+        fof.fof_build_cells(f.ctx, pos, w.offsets, w.box, w.lx)
+        fof.fof_link(f.ctx)
+        fof.fof_finalize(f.ctx, label, size)
+    torch.cuda.synchronize()
+    f.kernel_times()   # drop the warm-up record
+    start = event(torch, f.stream)
+    for _ in range(steps):
+        fof.fof_build_cells(f.ctx, pos, w.offsets, w.box, w.lx)
+        fof.fof_link(f.ctx)
+        fof.fof_finalize(f.ctx, label, size)
+    end = event(torch, f.stream)
+    torch.cuda.synchronize()
+    kt = f.kernel_times()
+    return start.elapsed_time(end) / steps, {k: (ms / max(1, c), c) for k, (ms, c) in kt.items() if c}
 
 
 def cpu_baseline(w):
@@ -122,8 +141,8 @@ def cpu_baseline(w):
     ref = oracle.fof(sub, lx)
     dt = time.perf_counter() - t0
     return sub, lx, ref, {"value": len(sub) / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
-                          "sample": f"sub-cube [0,1/2)^3 of {w.name} ({len(sub)} particles) scaled x2 into a unit box, "
-                                    f"l_x x2; single-threaded C oracle, {dt:.1f} s"}
+                          "sample": f"sub-cube [0,1/2)^3 of {w.name} ({len(sub)} particles) scaled x2 into a unit "
+                                    f"box, l_x x2; single-threaded C oracle, {dt:.1f} s"}
 
 
 def main():
@@ -137,6 +156,7 @@ def main():
 
     import paper_2003_11468_amd as fof
     import synth
+    from paper_2003_11468_amd import tune
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -146,18 +166,19 @@ def main():
     n = w.n
 
     # --- FP32 filter (the measured form) -----------------------------------
-    f = fof.FoF("fp32_filter", cell_factor=args.cell_factor)
+    log("tuning fp32_filter")
+    cfg = choose(torch, tune, pos, w, "fp32_filter", args)
+    f = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"], timings=True)
     label, size = f.outputs(n)
-    log("timing fp32_filter")
-    total, build, link, fin = time_pipeline(torch, fof, f, pos, w, args.steps, args.warmup, label, size)
-    ms = total / args.steps
+    log(f"timing fp32_filter cell_factor={cfg['cell_factor']} dense_min={cfg['dense_min']}")
+    ms, kern = timed_steps(torch, fof, f, pos, w, args.steps, args.warmup, label, size)
     groups = int(f.n_groups(w.n_boxes).sum())
     lab32 = label.cpu().numpy()
     size32 = size.cpu().numpy()
     f.close()
 
-    # pair-test count of the same configuration (stats build of the link pass)
-    fs = fof.FoF("fp32_filter", cell_factor=args.cell_factor, stats=True)
+    # counters of the same configuration (a separate stats run, not timed)
+    fs = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"], stats=True)
     fs.run(pos, w.offsets, w.box, w.lx)
     st = fs.stats()
     fs.close()
@@ -166,25 +187,43 @@ def main():
     plain = None
     exact = None
     if not args.no_plain:
-        log("timing fp64")
-        f64 = fof.FoF("fp64", cell_factor=args.cell_factor)
+        log("tuning fp64")
+        cfg64 = choose(torch, tune, pos, w, "fp64", args)
+        f64 = fof.FoF("fp64", cell_factor=cfg64["cell_factor"], dense_min=cfg64["dense_min"], timings=True)
         l64, s64 = f64.outputs(n)
-        t64, _, link64, _ = time_pipeline(torch, fof, f64, pos, w, max(3, args.steps // 2), 1, l64, s64)
-        ms64 = t64 / max(3, args.steps // 2)
+        log("timing fp64")
+        ms64, kern64 = timed_steps(torch, fof, f64, pos, w, max(3, args.steps // 2), 1, l64, s64)
         exact = bool(np.array_equal(l64.cpu().numpy(), lab32) and np.array_equal(s64.cpu().numpy(), size32))
         plain = {"value": n / (ms64 * 1e-3), "unit": "particles/s", "ms_per_step": ms64,
-                 "link_ms": statistics.median(link64), "fp32_speedup": ms64 / ms}
+                 "cell_factor": cfg64["cell_factor"], "dense_min": cfg64["dense_min"],
+                 "fp32_filter_speedup": ms64 / ms,
+                 "kernels_ms": {k: round(v[0], 4) for k, v in kern64.items()}}
         f64.close()
 
-    # --- roofline of the dominant kernel -----------------------------------
-    phase = {"build": statistics.median(build), "link": statistics.median(link), "finalize": statistics.median(fin)}
-    link_ms = phase["link"]
-    tests = st["pair_tests"]
-    achieved = tests * FLOP_PER_PAIR_TEST / (link_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": measured_traffic("k_link"),
-                "kernel": "k_link", "pair_tests": tests, "pair_tests_per_s": tests / (link_ms * 1e-3),
-                "kernel_ms": link_ms}
+    # --- roofline of the dominant kernel and HBM rates of the passes -------
+    nonroot = n - groups
+    passes = {}
+    for k, (avg_ms, count) in kern.items():
+        b = algorithmic_bytes(k, n, st["n_cells"], nonroot, st["queued_links"])
+        passes[k] = {"ms": round(avg_ms, 4)}
+        if b is not None:
+            passes[k]["GB/s"] = round(b / (avg_ms * 1e-3) / 1e9, 1)
+            passes[k]["hbm_frac"] = round(b / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)
+    dom = max(kern.items(), key=lambda kv: kv[1][0])[0]
+    dom_ms = kern[dom][0]
+    if dom in ("k_link_sparse", "k_link_dense"):
+        tests = st["sparse_pair_tests"] if dom == "k_link_sparse" else st["pair_tests"] - st["sparse_pair_tests"]
+        achieved = tests * FLOP_PER_PAIR_TEST / (dom_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": measured_traffic(dom), "kernel": dom,
+                    "kernel_ms": dom_ms, "pair_tests_per_launch": tests,
+                    "flop_per_pair_test": FLOP_PER_PAIR_TEST}
+    else:
+        b = algorithmic_bytes(dom, n, st["n_cells"], nonroot, st["queued_links"])
+        achieved = b / (dom_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom), "kernel": dom,
+                    "kernel_ms": dom_ms, "bytes_per_launch": b}
 
     # --- batched form --------------------------------------------------------
     batched = None
@@ -192,51 +231,58 @@ def main():
         log("generating batched256")
         wb = synth.make("batched256")
         pb = torch.from_numpy(wb.pos).to(dev)
-        fb = fof.FoF("fp32_filter")
+        log("tuning batched fp32_filter")
+        cfgb = choose(torch, tune, pb, wb, "fp32_filter", args)
+        fb = fof.FoF("fp32_filter", cell_factor=cfgb["cell_factor"], dense_min=cfgb["dense_min"])
         lb, sb = fb.outputs(wb.n)
         fb.capture(pb, wb.offsets, wb.box, wb.lx, lb, sb)
-        tm = Timer(torch, fb.stream)
         for _ in range(args.warmup):
             fb.replay()
         torch.cuda.synchronize()
         nb_steps = max(3, args.steps // 2)
-        e0 = tm.event()
+        e0 = event(torch, fb.stream)
         for _ in range(nb_steps):
             fb.replay()
-        e1 = tm.event()
+        e1 = event(torch, fb.stream)
         torch.cuda.synchronize()
         msb = e0.elapsed_time(e1) / nb_steps
         lab_b = lb.cpu().numpy()
         fb.close()
         batched = {"workload": "batched256", "n_boxes": wb.n_boxes, "n_particles": wb.n,
-                   "fp32_graph": {"value": wb.n / (msb * 1e-3), "ms_per_step": msb}}
+                   "fp32_graph": {"value": wb.n / (msb * 1e-3), "ms_per_step": msb,
+                                  "cell_factor": cfgb["cell_factor"], "dense_min": cfgb["dense_min"]}}
         if not args.no_plain:
             # plain path: FP64 predicate, one launch sequence per box, no graph
-            fp = fof.FoF("fp64")
+            log("timing batched fp64 per box")
+            cfgp = choose(torch, tune, pb, wb, "fp64", args)
+            fp = fof.FoF("fp64", cell_factor=cfgp["cell_factor"], dense_min=cfgp["dense_min"])
             lp, sp = fp.outputs(wb.n)
             sizes = np.diff(wb.offsets)
-            fp.reserve(np.array([0, int(sizes.max())]), 1.0, float(wb.lx.min()))
+            need = max(fof.fof_workspace_bytes(fp.ctx, [0, int(sizes[k])], wb.box[k], wb.lx[k])
+                       for k in range(wb.n_boxes))
+            fp.ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            fof.fof_set_workspace(fp.ctx, fp.ws)
             views = [(pb[wb.offsets[k]:wb.offsets[k + 1]], lp[wb.offsets[k]:wb.offsets[k + 1]],
                       sp[wb.offsets[k]:wb.offsets[k + 1]]) for k in range(wb.n_boxes)]
 
             def per_box():
                 for k, (pk, lk, sk) in enumerate(views):
-                    off = [0, int(sizes[k])]
-                    fof.fof_build_cells(fp.ctx, pk, off, wb.box[k], wb.lx[k])
+                    fof.fof_build_cells(fp.ctx, pk, [0, int(sizes[k])], wb.box[k], wb.lx[k])
                     fof.fof_link(fp.ctx)
                     fof.fof_finalize(fp.ctx, lk, sk)
 
             per_box()
             torch.cuda.synchronize()
-            e0 = tm.event()
+            e0 = event(torch, fp.stream)
             for _ in range(nb_steps):
                 per_box()
-            e1 = tm.event()
+            e1 = event(torch, fp.stream)
             torch.cuda.synchronize()
             msp = e0.elapsed_time(e1) / nb_steps
             same = bool(np.array_equal(lp.cpu().numpy(), lab_b))
-            batched["plain_fp64_per_box"] = {"value": wb.n / (msp * 1e-3), "ms_per_step": msp}
-            batched["speedup"] = msp / msb
+            batched["plain_fp64_per_box"] = {"value": wb.n / (msp * 1e-3), "ms_per_step": msp,
+                                             "cell_factor": cfgp["cell_factor"], "dense_min": cfgp["dense_min"]}
+            batched["speedup_vs_plain"] = msp / msb
             batched["exact_vs_plain"] = same
             fp.close()
 
@@ -246,7 +292,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         sub, lx_sub, ref, cpu = cpu_baseline(w)
-        lab_s, size_s, ng_s = fof.label(torch.from_numpy(sub).to(dev), lx_sub)
+        lab_s, size_s, ng_s = fof.label(torch.from_numpy(sub).to(dev), lx_sub, cell_factor=cfg["cell_factor"],
+                                        dense_min=cfg["dense_min"])
         sample_exact = bool(np.array_equal(lab_s.cpu().numpy(), ref[0]) and
                             np.array_equal(size_s.cpu().numpy(), ref[1]) and ng_s == ref[2])
 
@@ -265,10 +312,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_particles": n, "box": 1.0, "lx": float(w.lx[0]),
                    "b": w.meta.get("b"), "halo_frac": w.meta.get("halo_frac"), "predicate": "fp32_filter",
-                   "n_cells": st["n_cells"], "parallelism": "single GPU"},
-        "phases_ms": phase,
+                   "cell_factor": cfg["cell_factor"], "dense_min": cfg["dense_min"], "n_cells": st["n_cells"],
+                   "parallelism": "single GPU"},
         "n_groups": groups,
-        "stats": {k: st[k] for k in ("pair_tests", "links", "band_hits", "cas_retries")},
+        "kernels": passes,
+        "stats": {k: st[k] for k in ("pair_tests", "sparse_pair_tests", "links", "band_hits", "cas_retries",
+                                     "queued_links", "dense_items")},
         "guard_band_hit_fraction": {"per_test": st["band_hits"] / max(1, st["pair_tests"]),
                                     "per_link": st["band_hits"] / max(1, st["links"])},
         "roofline": roofline,

@@ -79,7 +79,9 @@ typedef struct {
     int32_t dense_min;       /* cells holding at least this many particles are searched by whole
                                 wavefronts (64 particles against broadcast candidates); the others
                                 per particle. 0 = default (32) */
-    int32_t reserved[6];     /* must be zero */
+    int32_t collect_timings; /* 1: record HIP events around every kernel launch on the context's
+                                stream (read with fof_get_kernel_times) */
+    int32_t reserved[5];     /* must be zero */
 } fof_options;
 
 typedef struct {
@@ -160,6 +162,21 @@ fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_
                              const double *h_box, const double *h_lx, int32_t n_boxes,
                              int32_t *d_group_index, int32_t *d_group_size);
 fof_status fof_graph_launch(fof_ctx *ctx);
+
+/* Waits for the stream and returns, per kernel of the pipeline, the summed
+ * device time (ms, from HIP events recorded around each launch on the
+ * context's stream) and the number of launches since the previous call; the
+ * record is then cleared. Needs fof_options.collect_timings = 1 (graph
+ * replays are not recorded). h_ms and h_launches (may be NULL) hold at least
+ * `capacity` entries; *n_kernels receives the number of kernels (names via
+ * fof_kernel_name). At most the latest 1024 launches are kept.
+ * Errors: FOF_ERR_INVALID_ARG (capacity too small), FOF_ERR_BAD_STATE
+ * (timings not enabled). */
+fof_status fof_get_kernel_times(fof_ctx *ctx, double *h_ms, int32_t *h_launches, int32_t capacity,
+                                int32_t *n_kernels);
+
+/* Name of kernel k of fof_get_kernel_times ("?" when out of range). */
+const char *fof_kernel_name(int32_t k);
 
 /* Releases the context, its graph and its pinned staging buffer (not the
  * caller's workspace). Waits for the stream. NULL is accepted. */

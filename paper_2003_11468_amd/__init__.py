@@ -37,7 +37,8 @@ class FoFError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("predicate", ctypes.c_int32), ("strict_less", ctypes.c_int32), ("cell_factor", ctypes.c_double),
-                ("collect_stats", ctypes.c_int32), ("dense_min", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("collect_stats", ctypes.c_int32), ("dense_min", ctypes.c_int32), ("collect_timings", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -54,7 +55,8 @@ class Stats(ctypes.Structure):
 _lib = None
 EXPORTS = ["fof_default_options", "fof_create", "fof_set_stream", "fof_workspace_bytes", "fof_set_workspace",
            "fof_build_cells", "fof_link", "fof_finalize", "fof_read_n_groups", "fof_get_stats",
-           "fof_graph_capture", "fof_graph_launch", "fof_destroy", "fof_status_string"]
+           "fof_graph_capture", "fof_graph_launch", "fof_destroy", "fof_status_string", "fof_get_kernel_times",
+           "fof_kernel_name"]
 
 
 def load_library():
@@ -82,6 +84,8 @@ def load_library():
         "fof_graph_launch": (ctypes.c_int, [vp]),
         "fof_destroy": (ctypes.c_int, [vp]),
         "fof_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "fof_get_kernel_times": (ctypes.c_int, [vp, f64p, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]),
+        "fof_kernel_name": (ctypes.c_char_p, [i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -201,6 +205,22 @@ def fof_destroy(ctx):
         _check(load_library().fof_destroy(ctx), "fof_destroy")
 
 
+def fof_get_kernel_times(ctx) -> dict:
+    """{kernel name: (ms summed, launches)} since the previous call."""
+    cap = 32
+    ms = np.zeros(cap, dtype=np.float64)
+    cnt = np.zeros(cap, dtype=np.int32)
+    nk = ctypes.c_int32()
+    _check(load_library().fof_get_kernel_times(ctx, _p(ms, ctypes.c_double), _p(cnt, ctypes.c_int32), cap,
+                                               ctypes.byref(nk)), "fof_get_kernel_times")
+    lib = load_library()
+    return {lib.fof_kernel_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(nk.value)}
+
+
+def fof_kernel_name(k: int) -> str:
+    return load_library().fof_kernel_name(k).decode()
+
+
 def fof_status_string(status: int) -> str:
     return load_library().fof_status_string(status).decode()
 
@@ -208,8 +228,9 @@ def fof_status_string(status: int) -> str:
 # ------------------------------------------------------ tensor wrapper --
 
 def make_options(predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
-                 stats: bool = False, dense_min: int = 0) -> Options:
+                 stats: bool = False, dense_min: int = 0, timings: bool = False) -> Options:
     o = fof_default_options()
+    o.collect_timings = int(timings)
     o.predicate = PREDICATES[predicate]
     o.strict_less = int(strict)
     o.cell_factor = float(cell_factor)
@@ -222,12 +243,13 @@ class FoF:
     """A context plus a workspace tensor, reused across calls of the same shape."""
 
     def __init__(self, predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
-                 stats: bool = False, stream=None, dense_min: int = 0):
+                 stats: bool = False, stream=None, dense_min: int = 0, timings: bool = False):
         import torch
 
         self._torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats, dense_min), self.stream.cuda_stream)
+        self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats, dense_min, timings),
+                              self.stream.cuda_stream)
         self.ws = None
 
     def close(self):
@@ -278,6 +300,9 @@ class FoF:
     def stats(self) -> dict:
         return fof_get_stats(self.ctx)
 
+    def kernel_times(self) -> dict:
+        return fof_get_kernel_times(self.ctx)
+
     def _check_pos(self, pos, offsets):
         t = self._torch
         if not (pos.is_cuda and pos.dtype == t.float32 and pos.dim() == 2 and pos.shape[1] == 3
@@ -288,9 +313,9 @@ class FoF:
 
 
 def label(pos, lx, box: float = 1.0, predicate: str = "fp32_filter", strict: bool = False,
-          cell_factor: float = 0.0):
+          cell_factor: float = 0.0, dense_min: int = 0):
     """Single periodic box: (group_index, group_size, n_groups)."""
-    f = FoF(predicate, strict, cell_factor)
+    f = FoF(predicate, strict, cell_factor, dense_min=dense_min)
     try:
         lab, size, ng = f.run(pos, [0, pos.shape[0]], box, lx)
         return lab, size, int(ng[0])
@@ -299,9 +324,9 @@ def label(pos, lx, box: float = 1.0, predicate: str = "fp32_filter", strict: boo
 
 
 def label_boxes(pos, offsets, box, lx, predicate: str = "fp32_filter", strict: bool = False,
-                cell_factor: float = 0.0):
+                cell_factor: float = 0.0, dense_min: int = 0):
     """Many independent boxes in one pass; labels are box-local."""
-    f = FoF(predicate, strict, cell_factor)
+    f = FoF(predicate, strict, cell_factor, dense_min=dense_min)
     try:
         return f.run(pos, offsets, box, lx)
     finally:

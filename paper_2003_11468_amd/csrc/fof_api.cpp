@@ -62,8 +62,49 @@ struct HostPlan {
 
 }  // namespace
 
+// Per-kernel HIP events: a ring of (start, stop) pairs, summed and reset by
+// fof_get_kernel_times. When more launches are recorded than the ring holds,
+// the oldest are overwritten and not counted.
+struct EventTimer final : fof::KernelTimer {
+    static constexpr int kSlots = 1024;
+    hipEvent_t start[kSlots] = {}, stop[kSlots] = {};
+    int kernel[kSlots] = {};
+    int next = 0, used = 0;
+    bool ok = false;
+    int pending_kernel = -1;
+
+    bool init()
+    {
+        for (int k = 0; k < kSlots; ++k) {
+            if (hipEventCreate(&start[k]) != hipSuccess || hipEventCreate(&stop[k]) != hipSuccess) return false;
+        }
+        ok = true;
+        return true;
+    }
+    ~EventTimer() override
+    {
+        for (int k = 0; k < kSlots; ++k) {
+            if (start[k]) (void)hipEventDestroy(start[k]);
+            if (stop[k]) (void)hipEventDestroy(stop[k]);
+        }
+    }
+    void mark(int k, bool end, hipStream_t s) override
+    {
+        if (!ok) return;
+        if (!end) {
+            kernel[next] = k;
+            (void)hipEventRecord(start[next], s);
+        } else {
+            (void)hipEventRecord(stop[next], s);
+            next = (next + 1) % kSlots;
+            if (used < kSlots) ++used;
+        }
+    }
+};
+
 struct fof_ctx {
     fof_options opt{};
+    EventTimer *timer = nullptr;
     hipStream_t stream = nullptr;
     int device = -1;
 
@@ -95,7 +136,8 @@ bool options_valid(const fof_options &o)
     if (!(o.cell_factor == 0.0 || (o.cell_factor >= 1.0 && std::isfinite(o.cell_factor)))) return false;
     if (o.collect_stats != 0 && o.collect_stats != 1) return false;
     if (o.dense_min < 0) return false;
-    for (int k = 0; k < 6; ++k)
+    if (o.collect_timings != 0 && o.collect_timings != 1) return false;
+    for (int k = 0; k < 5; ++k)
         if (o.reserved[k] != 0) return false;
     return true;
 }
@@ -295,6 +337,11 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
 fof_status do_build(fof_ctx *c, const float *d_pos, const int64_t *off, const double *box, const double *lx,
                     int32_t n_boxes)
 {
+    if (c->opt.collect_timings && !c->timer) {
+        if (ensure_device(c) != FOF_OK) return FOF_ERR_DEVICE;
+        c->timer = new (std::nothrow) EventTimer();
+        if (!c->timer || !c->timer->init()) return FOF_ERR_DEVICE;
+    }
     HostPlan np;
     fof_status st = make_plan(c, off, box, lx, n_boxes, &np);
     if (st != FOF_OK) return st;
@@ -307,8 +354,8 @@ fof_status do_build(fof_ctx *c, const float *d_pos, const int64_t *off, const do
 
 fof_status enqueue_build(fof_ctx *c, hipStream_t s)
 {
-    hipError_t e = fof::launch_clear(c->dev, s);
-    if (e == hipSuccess) e = fof::launch_build(c->dev, s);
+    hipError_t e = fof::launch_clear(c->dev, s, c->timer);
+    if (e == hipSuccess) e = fof::launch_build(c->dev, s, c->timer);
     return dev_err(e);
 }
 
@@ -403,7 +450,7 @@ fof_status fof_link(fof_ctx *ctx)
 {
     if (!ctx) return FOF_ERR_INVALID_ARG;
     if (ctx->state != 1) return FOF_ERR_BAD_STATE;
-    fof_status st = dev_err(fof::launch_link(ctx->dev, ctx->stream));
+    fof_status st = dev_err(fof::launch_link(ctx->dev, ctx->stream, ctx->timer));
     ctx->state = st == FOF_OK ? 2 : 0;
     return st;
 }
@@ -415,7 +462,7 @@ fof_status fof_finalize(fof_ctx *ctx, int32_t *d_group_index, int32_t *d_group_s
     if ((!d_group_index || !d_group_size) && ctx->plan.n > 0) return FOF_ERR_INVALID_ARG;
     ctx->dev.label = d_group_index;
     ctx->dev.size = d_group_size;
-    fof_status st = dev_err(fof::launch_finalize(ctx->dev, ctx->stream));
+    fof_status st = dev_err(fof::launch_finalize(ctx->dev, ctx->stream, ctx->timer));
     ctx->state = 0;   // the forest is consumed: a new build is needed
     if (st != FOF_OK) return st;
     if (h_n_groups) return read_back(ctx, h_n_groups, nullptr);
@@ -475,10 +522,11 @@ fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return FOF_ERR_DEVICE;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        e = fof::launch_clear(ctx->dev, cs);
-        if (e == hipSuccess) e = fof::launch_build(ctx->dev, cs);
-        if (e == hipSuccess) e = fof::launch_link(ctx->dev, cs);
-        if (e == hipSuccess) e = fof::launch_finalize(ctx->dev, cs);
+        // no per-kernel events inside a graph
+        e = fof::launch_clear(ctx->dev, cs, nullptr);
+        if (e == hipSuccess) e = fof::launch_build(ctx->dev, cs, nullptr);
+        if (e == hipSuccess) e = fof::launch_link(ctx->dev, cs, nullptr);
+        if (e == hipSuccess) e = fof::launch_finalize(ctx->dev, cs, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess) e = e2;
@@ -508,9 +556,37 @@ fof_status fof_destroy(fof_ctx *ctx)
     if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
+    delete ctx->timer;
     delete ctx;
     return FOF_OK;
 }
+
+fof_status fof_get_kernel_times(fof_ctx *ctx, double *h_ms, int32_t *h_launches, int32_t capacity,
+                                int32_t *n_kernels)
+{
+    if (!ctx || !n_kernels) return FOF_ERR_INVALID_ARG;
+    *n_kernels = fof::K_COUNT_KERNELS;
+    if (!h_ms || capacity < fof::K_COUNT_KERNELS) return FOF_ERR_INVALID_ARG;
+    for (int k = 0; k < fof::K_COUNT_KERNELS; ++k) {
+        h_ms[k] = 0.0;
+        if (h_launches) h_launches[k] = 0;
+    }
+    EventTimer *t = ctx->timer;
+    if (!t) return ctx->opt.collect_timings ? FOF_OK : FOF_ERR_BAD_STATE;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return FOF_ERR_DEVICE;
+    const int first = (t->next - t->used + EventTimer::kSlots) % EventTimer::kSlots;
+    for (int u = 0; u < t->used; ++u) {
+        const int slot = (first + u) % EventTimer::kSlots;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t->start[slot], t->stop[slot]) != hipSuccess) return FOF_ERR_DEVICE;
+        h_ms[t->kernel[slot]] += ms;
+        if (h_launches) h_launches[t->kernel[slot]] += 1;
+    }
+    t->used = 0;
+    return FOF_OK;
+}
+
+const char *fof_kernel_name(int32_t k) { return fof::kernel_name(k); }
 
 const char *fof_status_string(fof_status s)
 {

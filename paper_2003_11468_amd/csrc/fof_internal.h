@@ -77,10 +77,24 @@ int64_t scan_tiles_for(int64_t n_cells);
 // Capacity of the dense work-item list (fof_link.hip).
 int64_t max_dense_items(int64_t n, int dense_min);
 
-// Kernel launchers (fof_kernels.hip, fof_link.hip). All enqueue on `stream`.
-hipError_t launch_clear(const Plan &p, hipStream_t stream);
-hipError_t launch_build(const Plan &p, hipStream_t stream);
-hipError_t launch_link(const Plan &p, hipStream_t stream);
-hipError_t launch_finalize(const Plan &p, hipStream_t stream);
+// Kernels in launch order; the ids index per-kernel timings.
+enum KernelId {
+    K_CLEAR, K_COUNT, K_SCAN_REDUCE, K_SCAN_PARTIALS, K_SCAN_APPLY, K_SCATTER,
+    K_LINK_SPARSE, K_UNION_EDGES, K_LINK_DENSE, K_FLATTEN, K_RESOLVE, K_GATHER, K_COUNT_KERNELS
+};
+const char *kernel_name(int k);
+
+// Optional hook around every launch (records HIP events on the launch stream).
+struct KernelTimer {
+    virtual void mark(int kernel, bool end, hipStream_t stream) = 0;
+    virtual ~KernelTimer() = default;
+};
+
+// Kernel launchers (fof_kernels.hip, fof_link.hip). All enqueue on `stream`;
+// `t` may be null.
+hipError_t launch_clear(const Plan &p, hipStream_t stream, KernelTimer *t);
+hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t);
+hipError_t launch_link(const Plan &p, hipStream_t stream, KernelTimer *t);
+hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t);
 
 }  // namespace fof

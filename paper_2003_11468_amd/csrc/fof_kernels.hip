@@ -248,32 +248,52 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 
 }  // namespace
 
-hipError_t launch_clear(const Plan &p, hipStream_t stream)
+// Launch `k` bracketed by the timer marks.
+#define FOF_TIMED(id, ...)                 \
+    do {                                   \
+        if (t) t->mark(id, false, stream); \
+        __VA_ARGS__;                       \
+        if (t) t->mark(id, true, stream);  \
+    } while (0)
+
+const char *kernel_name(int k)
+{
+    static const char *names[K_COUNT_KERNELS] = {"k_clear", "k_count", "k_scan_reduce", "k_scan_partials",
+                                                 "k_scan_apply", "k_scatter", "k_link_sparse", "k_union_edges",
+                                                 "k_link_dense", "k_flatten", "k_resolve", "k_gather"};
+    return (k >= 0 && k < K_COUNT_KERNELS) ? names[k] : "?";
+}
+
+hipError_t launch_clear(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
     int64_t work = p.n_cells + 1 > p.n_boxes ? p.n_cells + 1 : p.n_boxes;
     unsigned g = grid_for(work);
     if (g > 65536u) g = 65536u;
-    hipLaunchKernelGGL(k_clear, dim3(g), dim3(kBlock), 0, stream, p);
+    FOF_TIMED(K_CLEAR, hipLaunchKernelGGL(k_clear, dim3(g), dim3(kBlock), 0, stream, p));
     return hipGetLastError();
 }
 
-hipError_t launch_build(const Plan &p, hipStream_t stream)
+hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
-    if (p.n > 0) hipLaunchKernelGGL(k_count, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)p.scan_tiles), dim3(kBlock), 0, stream, p);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kPartBlock), 0, stream, p);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)p.scan_tiles), dim3(kBlock), 0, stream, p);
-    if (p.n > 0) hipLaunchKernelGGL(k_scatter, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p);
+    if (p.n > 0) FOF_TIMED(K_COUNT, hipLaunchKernelGGL(k_count, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
+    FOF_TIMED(K_SCAN_REDUCE,
+              hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)p.scan_tiles), dim3(kBlock), 0, stream, p));
+    FOF_TIMED(K_SCAN_PARTIALS, hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kPartBlock), 0, stream, p));
+    FOF_TIMED(K_SCAN_APPLY,
+              hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)p.scan_tiles), dim3(kBlock), 0, stream, p));
+    if (p.n > 0)
+        FOF_TIMED(K_SCATTER, hipLaunchKernelGGL(k_scatter, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Plan &p, hipStream_t stream)
+hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
     if (p.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flatten, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p);
-    hipLaunchKernelGGL(k_resolve, dim3((unsigned)((p.n + kBlock * kOutItems - 1) / (kBlock * kOutItems))),
-                       dim3(kBlock), 0, stream, p);
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p);
+    FOF_TIMED(K_FLATTEN, hipLaunchKernelGGL(k_flatten, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
+    FOF_TIMED(K_RESOLVE,
+              hipLaunchKernelGGL(k_resolve, dim3((unsigned)((p.n + kBlock * kOutItems - 1) / (kBlock * kOutItems))),
+                                 dim3(kBlock), 0, stream, p));
+    FOF_TIMED(K_GATHER, hipLaunchKernelGGL(k_gather, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
     return hipGetLastError();
 }
 

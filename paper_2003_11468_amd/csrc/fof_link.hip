@@ -605,25 +605,31 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <bool kFP64, bool kStats>
-void launch_link_t(const Plan &p, hipStream_t stream)
+void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
+    if (t) t->mark(K_LINK_SPARSE, false, stream);
     hipLaunchKernelGGL((k_link_sparse<kFP64, kStats>), dim3((unsigned)p.sparse_blocks), dim3(kBlock), 0, stream, p);
+    if (t) t->mark(K_LINK_SPARSE, true, stream);
+    if (t) t->mark(K_UNION_EDGES, false, stream);
     hipLaunchKernelGGL((k_union_edges<kStats>), dim3(4096), dim3(kBlock), 0, stream, p);
+    if (t) t->mark(K_UNION_EDGES, true, stream);
+    if (t) t->mark(K_LINK_DENSE, false, stream);
     hipLaunchKernelGGL((k_link_dense<kFP64, kStats>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
+    if (t) t->mark(K_LINK_DENSE, true, stream);
 }
 
 }  // namespace
 
-hipError_t launch_link(const Plan &p, hipStream_t stream)
+hipError_t launch_link(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
     if (p.n == 0) return hipSuccess;
     const bool fp64 = p.predicate == 0;
     if (fp64) {
-        if (p.stats) launch_link_t<true, true>(p, stream);
-        else launch_link_t<true, false>(p, stream);
+        if (p.stats) launch_link_t<true, true>(p, stream, t);
+        else launch_link_t<true, false>(p, stream, t);
     } else {
-        if (p.stats) launch_link_t<false, true>(p, stream);
-        else launch_link_t<false, false>(p, stream);
+        if (p.stats) launch_link_t<false, true>(p, stream, t);
+        else launch_link_t<false, false>(p, stream, t);
     }
     return hipGetLastError();
 }

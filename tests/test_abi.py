@@ -143,3 +143,29 @@ def test_null_arguments():
             == fof.FOF_ERR_INVALID_ARG          # 4 particles but no position pointer
     finally:
         fof.fof_destroy(ctx)
+
+
+def test_kernel_times_need_the_option():
+    ctx = _ctx()
+    try:
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_get_kernel_times(ctx)
+        assert e.value.status == fof.FOF_ERR_BAD_STATE
+    finally:
+        fof.fof_destroy(ctx)
+    names = [fof.fof_kernel_name(k) for k in range(12)]
+    assert names[0] == "k_clear" and "k_link_dense" in names and fof.fof_kernel_name(99) == "?"
+
+
+def test_tune_workload_key_and_cache(tmp_path):
+    from paper_2003_11468_amd import tune
+
+    k1 = tune.workload_key([0, 256 ** 3], 1.0, 0.2 / 256, "fp32_filter")
+    k2 = tune.workload_key([0, 255 ** 3], 1.0, 0.2 / 255, "fp32_filter")
+    k3 = tune.workload_key([0, 256 ** 3], 1.0, 0.5 / 256, "fp32_filter")
+    assert k1 == k2 and k1 != k3 and "b0.2" in k1
+    assert tune.workload_key([0, 1000, 3000], [1.0, 1.0], [0.02, 0.02], "fp64").startswith("fp64|le|")
+    path = str(tmp_path / "t.json")
+    tune._save(path, {"a": {"cell_factor": 2.0, "dense_min": 16}})
+    assert tune._load(path)["a"]["dense_min"] == 16
+    assert tune._load(str(tmp_path / "missing.json")) == {}

@@ -286,3 +286,35 @@ def test_near_threshold_pairs_fp32_filter_is_exact():
         assert np.array_equal(size, ref[1]), predicate
         if st is not None:
             assert st["band_hits"] > 0
+
+
+def test_autotuner_choice_is_exact(tmp_path):
+    from paper_2003_11468_amd import tune
+
+    n = 200000
+    pos_np = synth.clustered(n, 21, 0, 0.6)
+    lx = synth.linking_length(0.2, n)
+    pos = torch.from_numpy(pos_np).cuda()
+    cache = str(tmp_path / "tune.json")
+    r = tune.autotune(pos, [0, n], 1.0, lx, cache_path=cache, repeats=1, cell_factors=(0.0, 2.0, 3.0),
+                      dense_mins=(8, 32))
+    assert not r["cached"] and len(r["tried"]) == 6
+    again = tune.autotune(pos, [0, n], 1.0, lx, cache_path=cache)
+    assert again["cached"] and again["cell_factor"] == r["cell_factor"]
+    assert_single(pos_np, lx, cell_factor=r["cell_factor"], dense_min=r["dense_min"])
+
+
+def test_kernel_times_cover_every_kernel():
+    n = 100000
+    pos = torch.from_numpy(synth.clustered(n, 3, 0, 0.6)).cuda()
+    f = fof.FoF(timings=True)
+    try:
+        for _ in range(3):
+            f.run(pos, [0, n], 1.0, synth.linking_length(0.2, n))
+        kt = f.kernel_times()
+        assert set(kt) == {fof.fof_kernel_name(k) for k in range(12)}
+        for name, (ms, launches) in kt.items():
+            assert launches == 3 and ms > 0.0, name
+        assert all(c == 0 for _, c in f.kernel_times().values())   # the record was cleared
+    finally:
+        f.close()
