@@ -42,14 +42,16 @@ def algorithmic_bytes(kernel: str, n: int, cells: int, nonroot: int, edges: int)
     """Bytes each HBM-bound pass must move at minimum (reads + writes)."""
     table = {
         "k_clear": 4 * cells,
-        "k_count": n * (12 + 8 + 12),            # xyz in; cell count RMW; slot, parent, size out
-        "k_scan_reduce": 4 * cells,
-        "k_scan_apply": 8 * cells,
-        "k_scatter": n * (12 + 4 + 4 + 16 + 8 + 4),  # xyz, slot, cell start in; sorted xyz, perm, slot map out
+        "k_bucket_hist": 12 * n,                  # xyz in (bucket histogram stays in LDS)
+        "k_bucket_scatter": n * (12 + 16 + 4),    # xyz in; staged xyz + index, staging slot out
+        "k_count": n * (16 + 8 + 12),             # staged particle in; cell count RMW; slot, parent, size out
+        "k_cell_scan": 12 * cells,                # counts read twice, starts written once
+        "k_scatter": n * (16 + 4 + 4 + 16 + 8 + 4),  # staged particle, slot, cell start in; sorted, perm, map out
         "k_union_edges": 8 * edges,
         "k_flatten": 4 * n + nonroot * (4 + 4 + 8),  # parent in; root out, perm in, two atomics per non-root
-        "k_resolve": n * (4 + 8 + 8),            # parent, perm in; label+size per slot out
-        "k_gather": n * (4 + 8 + 8),             # slot map, label+size in; label, size out
+        "k_resolve": n * (4 + 8 + 8),             # parent, perm in; label+size per slot out
+        "k_unsort": n * (4 + 8 + 8),              # slot map, label+size in; label+size per staging slot out
+        "k_gather": n * (4 + 8 + 8),              # staging slot, label+size in; label, size out
     }
     return table.get(kernel)
 

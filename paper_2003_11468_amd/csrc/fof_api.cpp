@@ -43,13 +43,16 @@ struct HostPlan {
     int64_t n = 0;
     int64_t n_cells = 0;
     int64_t scan_tiles = 0;
+    int64_t n_tiles = 0;
+    int32_t bucket_shift = 0, n_buckets = 1;
     int64_t fp64_boxes = 0;
     int64_t max_items = 0;
     std::vector<BoxDev> boxes;
     std::vector<int64_t> p0;
     // workspace layout (byte offsets)
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_rank = 0, o_sorted = 0,
-           o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, total = 0;
+           o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
+           o_stpos = 0, total = 0;
     int64_t max_edges = 0;
 
     bool same_geometry(const HostPlan &o) const
@@ -227,7 +230,17 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     }
     p.n = offsets[n_boxes];
     p.n_cells = cells;
-    p.scan_tiles = fof::scan_tiles_for(cells);
+    // buckets of consecutive cells for the two-level counting sort: at most 256
+    p.bucket_shift = 0;
+    while (((cells > 0 ? cells - 1 : 0) >> p.bucket_shift) >= 256) ++p.bucket_shift;
+    p.n_buckets = (int32_t)(((cells > 0 ? cells - 1 : 0) >> p.bucket_shift) + 1);
+    p.n_tiles = fof::sort_tiles_for(offsets[n_boxes]);
+    {
+        const int64_t a = fof::scan_scratch_for(cells + 1);
+        const int64_t b = fof::scan_scratch_for((int64_t)p.n_buckets * p.n_tiles);
+        p.scan_tiles = a > b ? a : b;
+    }
+    if ((int64_t)p.n_buckets * p.n_tiles > (int64_t)INT32_MAX) return FOF_ERR_UNSUPPORTED;
 
     const size_t n = (size_t)p.n;
     size_t o = 0;
@@ -253,6 +266,9 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     // the list full is merged on the spot instead
     p.max_edges = p.n > (1 << 20) ? p.n : (1 << 20);
     p.o_edges = take(sizeof(int32_t) * 2 * (size_t)p.max_edges);
+    p.o_hist = take(sizeof(int32_t) * (size_t)p.n_buckets * (size_t)p.n_tiles);
+    p.o_staging = take(sizeof(float) * 4 * n);
+    p.o_stpos = take(sizeof(int32_t) * n);
     p.total = o;
     *out = std::move(p);
     return FOF_OK;
@@ -312,6 +328,9 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.strict = c->opt.strict_less;
     d.stats = c->opt.collect_stats;
     d.scan_tiles = p.scan_tiles;
+    d.n_tiles = p.n_tiles;
+    d.bucket_shift = p.bucket_shift;
+    d.n_buckets = p.n_buckets;
     d.dense_min = dense_min_of(c->opt);
     d.dense_blocks = kDenseBlocks;
     d.sparse_blocks = kSparseBlocks;
@@ -331,6 +350,9 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.gsize = at<int32_t>(c->ws, p.o_gsize);
     d.items = at<int4>(c->ws, p.o_items);
     d.edges = at<int2>(c->ws, p.o_edges);
+    d.bucket_hist = at<int32_t>(c->ws, p.o_hist);
+    d.staging = at<float4>(c->ws, p.o_staging);
+    d.stpos = at<int32_t>(c->ws, p.o_stpos);
     return FOF_OK;
 }
 

@@ -43,7 +43,10 @@ struct Plan {
     int32_t predicate;      // 0 fp64, 1 fp32 filter
     int32_t strict;         // 1: r2 < l2
     int32_t stats;          // 1: count pair tests etc.
-    int64_t scan_tiles;     // tiles of the cell-count scan
+    int64_t scan_tiles;     // scratch ints for the tile sums of the scans
+    int64_t n_tiles;        // input tiles of the bucket pass (2048 particles each)
+    int32_t bucket_shift;   // bucket of a cell = cell >> bucket_shift
+    int32_t n_buckets;      // at most 256
     int32_t dense_min;      // cells with at least this many particles use the wave kernel
     int32_t dense_blocks;   // grid of the persistent dense link kernel
     int32_t sparse_blocks;  // grid of the persistent sparse link kernel
@@ -56,8 +59,11 @@ struct Plan {
     const int64_t *box_p0;  // [n_boxes + 1] particle offsets
 
     int32_t *cell;          // [n_cells + 1] counts, then exclusive prefix (cell start)
-    int32_t *scan_part;     // [scan_tiles] tile sums
-    int32_t *rank;          // [n] slot of particle i inside its cell; after the scatter its sorted slot
+    int32_t *scan_part;     // [scan_tiles] tile sums of every scan level
+    int32_t *bucket_hist;   // [n_buckets * n_tiles] counts, then output offsets (bucket-major)
+    float4 *staging;        // [n] bucket order: x, y, z, original index (bits); after the link: {label, size}
+    int32_t *stpos;         // [n] staging slot of input particle i
+    int32_t *rank;          // [n] per staging slot: slot inside its cell, after the scatter its sorted slot
     float4 *sorted;         // [n] cell-sorted x, y, z; after the link: {label, size} per sorted slot
     int2 *perm;             // [n] .x original index of sorted particle s, .y group minimum (at roots)
     int32_t *parent;        // [n] union-find forest over sorted indices
@@ -71,16 +77,18 @@ struct Plan {
     int32_t *size;          // [n] output, input order
 };
 
-// Tiles of the cell-count scan for n_cells cells (fof_kernels.hip).
-int64_t scan_tiles_for(int64_t n_cells);
+// Scratch ints the scans of `len` values need, and input tiles of the bucket
+// pass (fof_kernels.hip).
+int64_t scan_scratch_for(int64_t len);
+int64_t sort_tiles_for(int64_t n);
 
 // Capacity of the dense work-item list (fof_link.hip).
 int64_t max_dense_items(int64_t n, int dense_min);
 
 // Kernels in launch order; the ids index per-kernel timings.
 enum KernelId {
-    K_CLEAR, K_COUNT, K_SCAN_REDUCE, K_SCAN_PARTIALS, K_SCAN_APPLY, K_SCATTER,
-    K_LINK_SPARSE, K_UNION_EDGES, K_LINK_DENSE, K_FLATTEN, K_RESOLVE, K_GATHER, K_COUNT_KERNELS
+    K_CLEAR, K_BUCKET_HIST, K_BUCKET_SCAN, K_BUCKET_SCATTER, K_COUNT, K_CELL_SCAN, K_SCATTER,
+    K_LINK_SPARSE, K_UNION_EDGES, K_LINK_DENSE, K_FLATTEN, K_RESOLVE, K_UNSORT, K_GATHER, K_COUNT_KERNELS
 };
 const char *kernel_name(int k);
 
