@@ -52,7 +52,7 @@ struct HostPlan {
     // workspace layout (byte offsets)
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_rank = 0, o_sorted = 0,
            o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
-           o_stpos = 0, total = 0;
+           o_stpos = 0, o_wave_roots = 0, total = 0;
     int64_t max_edges = 0;
 
     bool same_geometry(const HostPlan &o) const
@@ -269,6 +269,7 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.o_hist = take(sizeof(int32_t) * (size_t)p.n_buckets * (size_t)p.n_tiles);
     p.o_staging = take(sizeof(float) * 4 * n);
     p.o_stpos = take(sizeof(int32_t) * n);
+    p.o_wave_roots = take(sizeof(int32_t) * ((n + 63) / 64));
     p.total = o;
     *out = std::move(p);
     return FOF_OK;
@@ -353,6 +354,8 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.bucket_hist = at<int32_t>(c->ws, p.o_hist);
     d.staging = at<float4>(c->ws, p.o_staging);
     d.stpos = at<int32_t>(c->ws, p.o_stpos);
+    d.wave_roots = at<int32_t>(c->ws, p.o_wave_roots);
+    d.n_waves = (p.n + 63) / 64;
     return FOF_OK;
 }
 

@@ -204,6 +204,21 @@ __device__ __forceinline__ int particle_cell(const BoxDev &bd, float x, float y,
     return (int)(bd.cell_base + ((int64_t)cz * nc + cy) * nc + cx);
 }
 
+// Work-groups are dispatched round-robin over the 8 XCDs, each with its own
+// L2. For kernels whose accesses are local in the tile index, tile t goes to
+// XCD t / per, so each XCD works through one contiguous range of tiles and
+// keeps that range's window in its own L2. Launch with 8 * per groups
+// (per = ceil(tiles / 8)); groups mapped past the last tile return.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_tile(int64_t group, int64_t groups)
+{
+    const int64_t per = groups / kXcds;
+    return (group % kXcds) * per + group / kXcds;
+}
+
+inline unsigned xcd_grid(int64_t tiles) { return (unsigned)(((tiles + kXcds - 1) / kXcds) * kXcds); }
+
 __device__ __forceinline__ const BoxDev &box_of(const Plan &p, int b)
 {
     return p.n_boxes == 1 ? p.box0 : p.boxes[b];

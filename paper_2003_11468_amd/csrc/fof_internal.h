@@ -63,6 +63,8 @@ struct Plan {
     int32_t *bucket_hist;   // [n_buckets * n_tiles] counts, then output offsets (bucket-major)
     float4 *staging;        // [n] bucket order: x, y, z, original index (bits); after the link: {label, size}
     int32_t *stpos;         // [n] staging slot of input particle i
+    int32_t *wave_roots;    // [n_waves] roots among the 64 sorted slots of each wave (resolve)
+    int64_t n_waves;
     int32_t *rank;          // [n] per staging slot: slot inside its cell, after the scatter its sorted slot
     float4 *sorted;         // [n] cell-sorted x, y, z; after the link: {label, size} per sorted slot
     int2 *perm;             // [n] .x original index of sorted particle s, .y group minimum (at roots)

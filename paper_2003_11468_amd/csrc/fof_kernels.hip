@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(kBlock) k_bucket_scatter(Plan p)
 // slots belong to the same bucket, so the atomics stay in a window of cells.
 __global__ void __launch_bounds__(kBlock) k_count(Plan p)
 {
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t k = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (k >= p.n) return;
     const float4 e = p.staging[k];
     const int i = __float_as_int(e.w);
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(ScanArgs a, Plan p)
 // In staging order into cell order; rank[k] becomes the sorted slot of staging slot k.
 __global__ void __launch_bounds__(kBlock) k_scatter(Plan p)
 {
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t k = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (k >= p.n) return;
     const float4 e = p.staging[k];
     const int i = __float_as_int(e.w);
@@ -305,43 +305,67 @@ __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
 
 // Resolve, in sorted order: out[s] = {group label (box-local), size at the
 // root's smallest member, else 0}. Reads are local (the root of s sits near
-// s in cell order) and the write is coalesced. Each thread handles kOutItems
-// particles spaced one block apart; roots are counted per box in registers and
-// flushed once per box change and at the end.
-constexpr int kOutItems = 8;
-
+// s in cell order) and the write is coalesced. Roots are counted per wave:
+// a wave inside one box stores its count in wave_roots[], one that straddles
+// boxes adds per lane; k_group_count sums wave_roots per box.
 __global__ void __launch_bounds__(kBlock) k_resolve(Plan p)
 {
-    const int64_t base = (int64_t)blockIdx.x * kBlock * kOutItems + threadIdx.x;
+    const int64_t s64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int2 *out = reinterpret_cast<int2 *>(p.sorted);   // positions are no longer needed
-    int cur_box = -1, cur_count = 0;
-    for (int k = 0; k < kOutItems; ++k) {
-        const int64_t s64 = base + (int64_t)k * kBlock;
-        if (s64 >= p.n) break;
+    bool root = false;
+    int b = 0;
+    if (s64 < p.n) {
         const int s = (int)s64;
-        const int b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, s64);
+        b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, s64);
         const int r = p.parent[s];
         const int o = p.perm[s].x;
-        const int m = p.perm[r].y;
+        const int2 pr = p.perm[r];
+        const int m = pr.y;
         const int p0 = p.n_boxes == 1 ? 0 : (int)p.box_p0[b];
         out[s] = make_int2(m - p0, (o == m) ? p.gsize[r] : 0);
-        if (r == s) {
-            if (b != cur_box) {
-                if (cur_count) atomicAdd(p.n_groups + cur_box, (unsigned long long)cur_count);
-                cur_box = b;
-                cur_count = 0;
-            }
-            ++cur_count;
-        }
+        root = r == s;
     }
-    wave_add_by_key(p.n_groups, cur_count ? cur_box : -1, (unsigned long long)cur_count);
+    const int64_t wave = s64 >> 6;
+    const int b0 = __shfl(b, 0, 64);
+    const bool one_box = __ballot(s64 < p.n && b != b0) == 0;
+    const int roots = __popcll(__ballot(root));
+    if (one_box) {
+        if (lane_id() == 0 && wave < p.n_waves) p.wave_roots[wave] = roots;
+    } else {
+        if (lane_id() == 0 && wave < p.n_waves) p.wave_roots[wave] = 0;
+        if (root) atomicAdd(p.n_groups + b, 1ull);
+    }
+}
+
+// n_groups[box] += sum of wave_roots over the waves of the box (a wave belongs
+// to the box of its first particle). One block per box, strided.
+__global__ void __launch_bounds__(kBlock) k_group_count(Plan p)
+{
+    __shared__ unsigned long long part[kBlock / 64];
+    for (int b = blockIdx.x; b < p.n_boxes; b += gridDim.x) {
+        const int64_t p0 = p.n_boxes == 1 ? 0 : p.box_p0[b];
+        const int64_t p1 = p.n_boxes == 1 ? p.n : p.box_p0[b + 1];
+        // waves whose first particle lies in [p0, p1)
+        const int64_t w0 = (p0 + 63) >> 6, w1 = (p1 + 63) >> 6;
+        unsigned long long sum = 0;
+        for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock) sum += (unsigned)p.wave_roots[w];
+        sum = wave_sum_u64(sum);
+        if (lane_id() == 0) part[threadIdx.x >> 6] = sum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int k = 0; k < kBlock / 64; ++k) t += part[k];
+            if (t) atomicAdd(p.n_groups + b, t);
+        }
+        __syncthreads();
+    }
 }
 
 // Back into staging order: the sorted slots of a bucket's staging slots lie in
 // that bucket's window, so the reads stay local.
 __global__ void __launch_bounds__(kBlock) k_unsort(Plan p)
 {
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t k = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (k >= p.n) return;
     const int2 *out = reinterpret_cast<const int2 *>(p.sorted);
     int2 *staged = reinterpret_cast<int2 *>(p.staging);   // staging positions are no longer needed
@@ -361,6 +385,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(Plan p)
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+inline int64_t grid_tiles(int64_t n) { return (n + kBlock - 1) / kBlock; }
 
 // Exclusive scan of data[0, len) in place; `scratch` holds the tile sums of
 // every level (scan_scratch_for(len) ints).
@@ -425,11 +450,13 @@ hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t)
                   scan_exclusive(p.bucket_hist, (int64_t)p.n_buckets * p.n_tiles, p.scan_part, p, false, stream));
         FOF_TIMED(K_BUCKET_SCATTER,
                   hipLaunchKernelGGL(k_bucket_scatter, dim3(tiles), dim3(kBlock), 0, stream, p));
-        FOF_TIMED(K_COUNT, hipLaunchKernelGGL(k_count, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
+        FOF_TIMED(K_COUNT,
+                  hipLaunchKernelGGL(k_count, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p));
     }
     FOF_TIMED(K_CELL_SCAN, scan_exclusive(p.cell, p.n_cells + 1, p.scan_part, p, true, stream));
     if (p.n > 0)
-        FOF_TIMED(K_SCATTER, hipLaunchKernelGGL(k_scatter, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
+        FOF_TIMED(K_SCATTER,
+                  hipLaunchKernelGGL(k_scatter, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p));
     return hipGetLastError();
 }
 
@@ -437,10 +464,11 @@ hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
     if (p.n == 0) return hipSuccess;
     FOF_TIMED(K_FLATTEN, hipLaunchKernelGGL(k_flatten, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
-    FOF_TIMED(K_RESOLVE,
-              hipLaunchKernelGGL(k_resolve, dim3((unsigned)((p.n + kBlock * kOutItems - 1) / (kBlock * kOutItems))),
-                                 dim3(kBlock), 0, stream, p));
-    FOF_TIMED(K_UNSORT, hipLaunchKernelGGL(k_unsort, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
+    FOF_TIMED(K_RESOLVE, {
+        hipLaunchKernelGGL(k_resolve, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p);
+        hipLaunchKernelGGL(k_group_count, dim3((unsigned)min(p.n_boxes, 4096)), dim3(kBlock), 0, stream, p);
+    });
+    FOF_TIMED(K_UNSORT, hipLaunchKernelGGL(k_unsort, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p));
     FOF_TIMED(K_GATHER, hipLaunchKernelGGL(k_gather, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
     return hipGetLastError();
 }
