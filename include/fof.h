@@ -99,6 +99,22 @@ typedef struct {
     int64_t reserved[5];
 } fof_stats;
 
+/* Geometry and FP32 decision thresholds the library uses for one box. */
+typedef struct {
+    int64_t cells_per_axis;  /* n_c: cells of side L / n_c per axis */
+    double l2;               /* l_x * l_x, rounded once (the double predicate's threshold) */
+    float lo32;              /* FP32 squared distance below this: linked, proven */
+    float hi32;              /* FP32 squared distance above this: not linked, proven */
+    int32_t fp64_only;       /* 1: the FP32 filter cannot be proven for this box; every pair is
+                                decided in double */
+    int32_t reserved[3];
+} fof_box_info;
+
+/* Host only: the cell count per axis and FP32 thresholds for a box of
+ * `n_particles` particles, side `box` and linking length `lx` under options
+ * `opt` (NULL = defaults). Same validation as fof_workspace_bytes. */
+fof_status fof_describe_box(const fof_options *opt, int64_t n_particles, double box, double lx, fof_box_info *out);
+
 /* Fills *opt with the defaults: FP32 filter, r2 <= l2, automatic cells, no stats. */
 void fof_default_options(fof_options *opt);
 

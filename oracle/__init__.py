@@ -58,6 +58,9 @@ def _load():
     lib.oracle_component.argtypes = [ctypes.c_int64, f32p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                      ctypes.c_int64, i32p, ctypes.c_int64]
     lib.oracle_component.restype = ctypes.c_int64
+    lib.oracle_components_of.argtypes = [ctypes.c_int64, f32p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                         i64p, ctypes.c_int32, i32p, i64p, i32p]
+    lib.oracle_components_of.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -133,3 +136,19 @@ def component(pos, lx: float, start: int, box: float = 1.0, strict: bool = False
         if c <= cap:
             return out[:c].copy()
         cap = int(c)
+
+
+def components_of(pos, lx: float, starts, box: float = 1.0, strict: bool = False):
+    """Groups of several start particles by breadth-first search over one cell
+    list: (sizes[k], minimum index[k], mark) with mark[i] = k for the members
+    found from start k (-1 elsewhere; a start inside an earlier start's group
+    gets that group's size and minimum and marks nothing)."""
+    p = _pos(pos)
+    st = np.ascontiguousarray(starts, dtype=np.int64)
+    mark = np.empty(len(p), dtype=np.int32)
+    sizes = np.zeros(len(st), dtype=np.int64)
+    mins = np.zeros(len(st), dtype=np.int32)
+    _check(_load().oracle_components_of(len(p), _p(p, ctypes.c_float), float(box), float(lx), int(strict),
+                                        _p(st, ctypes.c_int64), len(st), _p(mark, ctypes.c_int32),
+                                        _p(sizes, ctypes.c_int64), _p(mins, ctypes.c_int32)))
+    return sizes, mins, mark

@@ -305,3 +305,77 @@ int64_t oracle_component(int64_t n, const float *pos, double L, double lx, int s
     free(queue);
     return count;
 }
+
+/* Breadth-first search from several start particles over one cell list. For
+ * start k: sizes[k] = size of its group, mins[k] = smallest index in it;
+ * mark[i] = k for the members found from start k (-1 elsewhere). A start that
+ * lies in a group already searched from an earlier start k' gets the sizes
+ * and minimum of k' and leaves mark untouched. Returns 0 or a negative status. */
+int oracle_components_of(int64_t n, const float *pos, double L, double lx, int strict, const int64_t *starts,
+                         int32_t k, int32_t *mark, int64_t *sizes, int32_t *mins)
+{
+    int st = validate(n, pos, L, lx);
+    if (st) return st;
+    const double l2 = lx * lx;
+    const int64_t nc = oracle_cells_per_axis(n, L, lx);
+    int32_t *head = NULL, *next = NULL;
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!queue) return ORACLE_ERR_MEM;
+    for (int64_t i = 0; i < n; ++i) mark[i] = -1;
+    if (nc > 0) {
+        const int64_t ncell = nc * nc * nc;
+        head = (int32_t *)malloc(sizeof(int32_t) * (size_t)ncell);
+        next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        if (!head || !next) { free(head); free(next); free(queue); return ORACLE_ERR_MEM; }
+        for (int64_t c = 0; c < ncell; ++c) head[c] = -1;
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t c = (cell_of(pos[3 * i + 2], nc, L) * nc + cell_of(pos[3 * i + 1], nc, L)) * nc +
+                        cell_of(pos[3 * i + 0], nc, L);
+            next[i] = head[c];
+            head[c] = (int32_t)i;
+        }
+    }
+    for (int32_t s = 0; s < k; ++s) {
+        const int64_t start = starts[s];
+        if (start < 0 || start >= n) { free(head); free(next); free(queue); return ORACLE_ERR_N; }
+        if (mark[start] >= 0) {
+            sizes[s] = sizes[mark[start]];
+            mins[s] = mins[mark[start]];
+            continue;
+        }
+        int64_t qh = 0, qt = 0;
+        int32_t lo = (int32_t)start;
+        queue[qt++] = (int32_t)start;
+        mark[start] = s;
+        while (qh < qt) {
+            const int64_t i = queue[qh++];
+            if (i < lo) lo = (int32_t)i;
+            if (nc == 0) {
+                for (int64_t j = 0; j < n; ++j)
+                    if (mark[j] < 0 && linked(pos + 3 * i, pos + 3 * j, L, l2, strict)) {
+                        mark[j] = s;
+                        queue[qt++] = (int32_t)j;
+                    }
+                continue;
+            }
+            const int64_t cx = cell_of(pos[3 * i + 0], nc, L), cy = cell_of(pos[3 * i + 1], nc, L),
+                          cz = cell_of(pos[3 * i + 2], nc, L);
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int64_t ox = (cx + dx + nc) % nc, oy = (cy + dy + nc) % nc, oz = (cz + dz + nc) % nc;
+                        for (int64_t j = head[(oz * nc + oy) * nc + ox]; j >= 0; j = next[j])
+                            if (mark[j] < 0 && linked(pos + 3 * i, pos + 3 * j, L, l2, strict)) {
+                                mark[j] = s;
+                                queue[qt++] = (int32_t)j;
+                            }
+                    }
+        }
+        sizes[s] = qt;
+        mins[s] = lo;
+    }
+    free(head);
+    free(next);
+    free(queue);
+    return ORACLE_OK;
+}

@@ -52,11 +52,16 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class BoxInfo(ctypes.Structure):
+    _fields_ = [("cells_per_axis", ctypes.c_int64), ("l2", ctypes.c_double), ("lo32", ctypes.c_float),
+                ("hi32", ctypes.c_float), ("fp64_only", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
 _lib = None
 EXPORTS = ["fof_default_options", "fof_create", "fof_set_stream", "fof_workspace_bytes", "fof_set_workspace",
            "fof_build_cells", "fof_link", "fof_finalize", "fof_read_n_groups", "fof_get_stats",
            "fof_graph_capture", "fof_graph_launch", "fof_destroy", "fof_status_string", "fof_get_kernel_times",
-           "fof_kernel_name"]
+           "fof_kernel_name", "fof_describe_box"]
 
 
 def load_library():
@@ -86,6 +91,8 @@ def load_library():
         "fof_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "fof_get_kernel_times": (ctypes.c_int, [vp, f64p, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]),
         "fof_kernel_name": (ctypes.c_char_p, [i32]),
+        "fof_describe_box": (ctypes.c_int, [ctypes.POINTER(Options), i64, ctypes.c_double, ctypes.c_double,
+                                            ctypes.POINTER(BoxInfo)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -215,6 +222,14 @@ def fof_get_kernel_times(ctx) -> dict:
                                                ctypes.byref(nk)), "fof_get_kernel_times")
     lib = load_library()
     return {lib.fof_kernel_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(nk.value)}
+
+
+def fof_describe_box(n_particles: int, box: float, lx: float, opt: Options | None = None) -> dict:
+    """Host only: cells per axis and the FP32 decision thresholds for one box."""
+    info = BoxInfo()
+    _check(load_library().fof_describe_box(ctypes.byref(opt) if opt is not None else None, int(n_particles),
+                                           float(box), float(lx), ctypes.byref(info)), "fof_describe_box")
+    return {k: getattr(info, k) for k, _ in info._fields_ if k != "reserved"}
 
 
 def fof_kernel_name(k: int) -> str:

@@ -586,6 +586,32 @@ fof_status fof_destroy(fof_ctx *ctx)
     return FOF_OK;
 }
 
+fof_status fof_describe_box(const fof_options *opt, int64_t n_particles, double box, double lx, fof_box_info *out)
+{
+    if (!out) return FOF_ERR_INVALID_ARG;
+    std::memset(out, 0, sizeof(*out));
+    fof_options o;
+    fof_default_options(&o);
+    if (opt) o = *opt;
+    if (!options_valid(o)) return FOF_ERR_INVALID_ARG;
+    if (n_particles < 0 || n_particles > (int64_t)INT32_MAX) return FOF_ERR_INVALID_ARG;
+    if (!(box > 0.0) || !std::isfinite(box) || !(lx > 0.0) || !std::isfinite(lx)) return FOF_ERR_INVALID_ARG;
+    int64_t nc = 0;
+    fof_status st = cells_per_axis(o, n_particles, box, lx, &nc);
+    if (st != FOF_OK) return st;
+    BoxDev b;
+    std::memset(&b, 0, sizeof(b));
+    b.L = box;
+    b.l2 = lx * lx;
+    fp32_thresholds(b, lx);
+    out->cells_per_axis = nc;
+    out->l2 = b.l2;
+    out->lo32 = b.lo32;
+    out->hi32 = b.hi32;
+    out->fp64_only = b.use_fp64;
+    return FOF_OK;
+}
+
 fof_status fof_get_kernel_times(fof_ctx *ctx, double *h_ms, int32_t *h_launches, int32_t capacity,
                                 int32_t *n_kernels)
 {

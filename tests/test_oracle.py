@@ -234,6 +234,19 @@ def test_component_bfs_matches_union_find():
         assert np.array_equal(members, np.flatnonzero(label == label[start]))
 
 
+def test_components_of_match_union_find():
+    n = 30000
+    pos = synth.clustered(n, 41, 0, 0.6)
+    lx = synth.linking_length(0.3, n)
+    label, size, _ = oracle.fof(pos, lx)
+    starts = [int(np.argmax(size)), 7, 123, int(np.argmax(size)) + 0, 29999]
+    sizes, mins, mark = oracle.components_of(pos, lx, starts)
+    for k, s in enumerate(starts):
+        assert mins[k] == label[s] and sizes[k] == size[label[s]]
+        first = next(q for q in range(k + 1) if mark[starts[q]] == mark[s])
+        assert np.array_equal(np.flatnonzero(mark == first), np.flatnonzero(label == label[s]))
+
+
 def test_boxes_equal_single_box_runs():
     w = synth.make("batched256", n_boxes=6, size_scale=0.02)
     lab1, size1, ng1 = oracle.fof_boxes(w.pos, w.offsets, w.box, w.lx, threads=1)
