@@ -52,7 +52,7 @@ struct HostPlan {
     // workspace layout (byte offsets)
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_rank = 0, o_sorted = 0,
            o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
-           o_stpos = 0, o_wave_roots = 0, total = 0;
+           o_stpos = 0, o_wave_roots = 0, o_occ = 0, o_edge_fill = 0, total = 0;
     int64_t max_edges = 0;
 
     bool same_geometry(const HostPlan &o) const
@@ -265,11 +265,14 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     // linked pairs of sparse cells, merged after the search; a pair that finds
     // the list full is merged on the spot instead
     p.max_edges = p.n > (1 << 20) ? p.n : (1 << 20);
+    p.max_edges = (p.max_edges + fof::kEdgeSlices - 1) / fof::kEdgeSlices * fof::kEdgeSlices;
     p.o_edges = take(sizeof(int32_t) * 2 * (size_t)p.max_edges);
+    p.o_edge_fill = take(sizeof(uint32_t) * fof::kEdgeSlices);
     p.o_hist = take(sizeof(int32_t) * (size_t)p.n_buckets * (size_t)p.n_tiles);
     p.o_staging = take(sizeof(float) * 4 * n);
     p.o_stpos = take(sizeof(int32_t) * n);
     p.o_wave_roots = take(sizeof(int32_t) * ((n + 63) / 64));
+    p.o_occ = take(sizeof(uint32_t) * ((size_t)(cells + 1) / 32 + 2));
     p.total = o;
     *out = std::move(p);
     return FOF_OK;
@@ -355,6 +358,8 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.staging = at<float4>(c->ws, p.o_staging);
     d.stpos = at<int32_t>(c->ws, p.o_stpos);
     d.wave_roots = at<int32_t>(c->ws, p.o_wave_roots);
+    d.occ = at<uint32_t>(c->ws, p.o_occ);
+    d.edge_fill = at<unsigned int>(c->ws, p.o_edge_fill);
     d.n_waves = (p.n + 63) / 64;
     return FOF_OK;
 }

@@ -219,6 +219,22 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t group, int64_t groups)
 
 inline unsigned xcd_grid(int64_t tiles) { return (unsigned)(((tiles + kXcds - 1) / kXcds) * kXcds); }
 
+// Persistent kernels: the waves of XCD x (groups g with g % 8 == x) share the
+// contiguous work range [x * span, (x + 1) * span), span = ceil(total / 8).
+// Call with a grid that is a multiple of 8.
+struct XcdRange {
+    int64_t first, end, stride;
+};
+
+__device__ __forceinline__ XcdRange xcd_range(int64_t total, int waves_per_group, int wave_in_group)
+{
+    const int64_t xcd = blockIdx.x % kXcds, g = blockIdx.x / kXcds, groups = gridDim.x / kXcds;
+    const int64_t span = (total + kXcds - 1) / kXcds;
+    const int64_t lo = xcd * span;
+    const int64_t hi = lo + span < total ? lo + span : total;
+    return {lo + g * waves_per_group + wave_in_group, hi, groups * waves_per_group};
+}
+
 __device__ __forceinline__ const BoxDev &box_of(const Plan &p, int b)
 {
     return p.n_boxes == 1 ? p.box0 : p.boxes[b];

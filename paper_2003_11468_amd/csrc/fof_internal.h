@@ -6,6 +6,10 @@
 
 namespace fof {
 
+// The edge list is split into slices with a counter each, so that no single
+// address takes every append.
+constexpr int kEdgeSlices = 256;
+
 // Per-box parameters as the kernels see them (one entry per box).
 struct BoxDev {
     int64_t p0, p1;       // particle range [p0, p1): input and sorted order use the same range
@@ -31,7 +35,7 @@ struct Counters {
     unsigned long long sparse_tests;   // pair tests of the per-lane (sparse) search
     unsigned int error;         // bit 0: coordinate outside [0, L) or not finite
     unsigned int n_items;       // work items of the dense link kernel
-    unsigned int n_edges;       // linked pairs queued for the union kernel (may exceed capacity)
+    unsigned int n_edges;       // linked pairs queued for the union kernel (summed after the search)
     unsigned int pad[5];
 };
 
@@ -51,7 +55,7 @@ struct Plan {
     int32_t dense_blocks;   // grid of the persistent dense link kernel
     int32_t sparse_blocks;  // grid of the persistent sparse link kernel
     int64_t max_items;      // capacity of `items`
-    int64_t max_edges;      // capacity of `edges`
+    int64_t max_edges;      // capacity of `edges`: kEdgeSlices slices of max_edges / kEdgeSlices
 
     BoxDev box0;            // the box itself when n_boxes == 1 (no table read)
     const float *pos;       // [n][3] input
@@ -63,6 +67,7 @@ struct Plan {
     int32_t *bucket_hist;   // [n_buckets * n_tiles] counts, then output offsets (bucket-major)
     float4 *staging;        // [n] bucket order: x, y, z, original index (bits); after the link: {label, size}
     int32_t *stpos;         // [n] staging slot of input particle i
+    uint32_t *occ;          // [(n_cells + 1) / 32 + 2] bit c: cell c holds a particle (cell scan)
     int32_t *wave_roots;    // [n_waves] roots among the 64 sorted slots of each wave (resolve)
     int64_t n_waves;
     int32_t *rank;          // [n] per staging slot: slot inside its cell, after the scatter its sorted slot
@@ -72,6 +77,7 @@ struct Plan {
     int32_t *gsize;         // [n] group member count at roots (sorted indices)
     int4 *items;            // [max_items] dense work: {cell, first home particle, box, 0}
     int2 *edges;            // [max_edges] linked pairs found by the sparse search
+    unsigned int *edge_fill;   // [kEdgeSlices] pairs appended to each slice (may exceed its capacity)
     unsigned long long *n_groups;  // [n_boxes]
     Counters *counters;
 

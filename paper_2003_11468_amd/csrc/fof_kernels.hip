@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(kBlock) k_clear(Plan p)
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i <= p.n_cells; i += stride) p.cell[i] = 0;
     int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < p.n_boxes) p.n_groups[t] = 0;
+    if (t < kEdgeSlices) p.edge_fill[t] = 0;
     if (t == 0) {
         p.counters->pair_tests = 0;
         p.counters->links = 0;
@@ -246,6 +247,13 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(ScanArgs a, Plan p)
             if (base + k < a.len) a.data[base + k] = o[k];
     }
     if (kCells) {
+        // occupancy bits: the 8 cells of 4 consecutive threads form one word
+        unsigned bits = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) bits |= (v[k] > 0 ? 1u : 0u) << k;
+        const int lane = lane_id();
+        const unsigned b1 = __shfl_down(bits, 1, 64), b2 = __shfl_down(bits, 2, 64), b3 = __shfl_down(bits, 3, 64);
+        if ((lane & 3) == 0 && base < a.len) p.occ[base >> 5] = bits | (b1 << 8) | (b2 << 16) | (b3 << 24);
         // one atomic per wave reserves the item slots
         const int incl = wave_incl_scan(chunks);
         const int wave_total = __shfl(incl, 63, 64);

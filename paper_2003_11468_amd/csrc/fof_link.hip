@@ -147,18 +147,22 @@ struct EdgeSink {
         if (count >= 64) flush(p, retries);
     }
 
+    // Appends the buffer to this work-group's slice of the edge list (one
+    // atomic on the slice counter); pairs that find the slice full are merged here.
     __device__ __forceinline__ void flush(const Plan &p, unsigned &retries)
     {
         if (count == 0) return;
         const int lane = lane_id();
+        const int slice = blockIdx.x % kEdgeSlices;
+        const int64_t cap = p.max_edges / kEdgeSlices;
         unsigned base = 0;
-        if (lane == 0) base = atomicAdd(&p.counters->n_edges, (unsigned)count);
+        if (lane == 0) base = atomicAdd(&p.edge_fill[slice], (unsigned)count);
         base = (unsigned)__shfl((int)base, 0, 64);
         for (int k = lane; k < count; k += 64) {
             const int2 e = buf[k];
-            const unsigned at = base + (unsigned)k;
-            if ((int64_t)at < p.max_edges) p.edges[at] = e;
-            else retries += unite(p.parent, e.x, e.y);   // list full: merge here
+            const int64_t at = (int64_t)base + k;
+            if (at < cap) p.edges[slice * cap + at] = e;
+            else retries += unite(p.parent, e.x, e.y);
         }
         __builtin_amdgcn_wave_barrier();
         count = 0;
@@ -188,7 +192,10 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
     unsigned long long tests = 0, links = 0, band = 0;
     unsigned retries = 0;
     const int64_t n_tiles = (p.n + 63) / 64;
-    for (int64_t tile = (int64_t)blockIdx.x * kWaves + wid; tile < n_tiles; tile += (int64_t)gridDim.x * kWaves) {
+    // each XCD sweeps one contiguous range of tiles, so the neighbour rows of
+    // consecutive tiles are reused from its own L2
+    const XcdRange xr = xcd_range(n_tiles, kWaves, wid);
+    for (int64_t tile = xr.first; tile < xr.end; tile += xr.stride) {
         const int64_t s64 = tile * 64 + lane;
         Ranges R;
         float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -210,9 +217,17 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
             // Boundaries of the own row and the four neighbour rows (dy, dz) =
             // (1, 0), (-1, 1), (0, 1), (1, 1): with the own cell these hold the
             // 13 half-shell cells. All are requested before any is used.
+            // Occupancy bits first (one bit per cell, a small array that stays
+            // in cache): boundaries are read only for rows with a particle.
+            const uint32_t *occ = p.occ;
+            auto occupied = [&](int cell_index) { return (occ[cell_index >> 5] >> (cell_index & 31)) & 1u; };
             const int own_start = cell[c], own_end = cell[c + 1];
             const int nxp = cx + 1 < nc ? cx + 1 : 0;
-            const int nxt_start = cell[rb0 + nxp], nxt_end = cell[rb0 + nxp + 1];
+            int nxt_start = 0, nxt_end = 0;
+            if (occupied(rb0 + nxp)) {
+                nxt_start = cell[rb0 + nxp];
+                nxt_end = cell[rb0 + nxp + 1];
+            }
             const bool inner = cx >= 1 && cx + 1 < nc;
             const int rdy[4] = {1, -1, 0, 1}, rdz[4] = {0, 1, 1, 1};
             int st[4][3], en[4][3], yz[4];
@@ -224,19 +239,27 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
                 if (nz >= nc) { nz -= nc; code |= 2 << 4; }
                 yz[r] = code;
                 const int rb = cb + (nz * nc + ny) * nc;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) st[r][e] = en[r][e] = 0;
                 if (inner) {
-                    typedef int int4a4 __attribute__((ext_vector_type(4), aligned(4)));
-                    const int4a4 q = *reinterpret_cast<const int4a4 *>(cell + rb + cx - 1);
-                    st[r][0] = q.x; en[r][0] = q.y;
-                    st[r][1] = q.y; en[r][1] = q.z;
-                    st[r][2] = q.z; en[r][2] = q.w;
+                    const int c0 = rb + cx - 1;
+                    const uint64_t w = (uint64_t)occ[c0 >> 5] | ((uint64_t)occ[(c0 >> 5) + 1] << 32);
+                    if ((w >> (c0 & 31)) & 7u) {
+                        typedef int int4a4 __attribute__((ext_vector_type(4), aligned(4)));
+                        const int4a4 q = *reinterpret_cast<const int4a4 *>(cell + c0);
+                        st[r][0] = q.x; en[r][0] = q.y;
+                        st[r][1] = q.y; en[r][1] = q.z;
+                        st[r][2] = q.z; en[r][2] = q.w;
+                    }
                 } else {
 #pragma unroll
                     for (int e = 0; e < 3; ++e) {
                         int nx = cx - 1 + e;
                         nx += nx < 0 ? nc : (nx >= nc ? -nc : 0);
-                        st[r][e] = cell[rb + nx];
-                        en[r][e] = cell[rb + nx + 1];
+                        if (occupied(rb + nx)) {
+                            st[r][e] = cell[rb + nx];
+                            en[r][e] = cell[rb + nx + 1];
+                        }
                     }
                 }
             }
@@ -284,67 +307,83 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
         const int b0 = __builtin_amdgcn_readfirstlane(b);
         const bool one_box = __ballot(b != b0) == 0;
         const bool strict = p.strict != 0;
-        // Each step takes kLanePairs pairs per lane (consecutive chunks of 64),
-        // so their unit searches and candidate loads overlap.
-        constexpr int kLanePairs = 4;
-        for (int base = 0; base < n_pairs; base += 64 * kLanePairs) {
-            int unit[kLanePairs];
+        // Merge-path split: lane l takes the pairs [T l / 64, T (l + 1) / 64) of
+        // the wave's T pairs, finds the unit of its first pair by one binary
+        // search, then walks forward; every lane runs the same number of steps.
+        const int q0 = (int)(((int64_t)n_pairs * lane) >> 6);
+        const int q1 = (int)(((int64_t)n_pairs * (lane + 1)) >> 6);
+        int u = 0;
 #pragma unroll
-            for (int k = 0; k < kLanePairs; ++k) {
-                const int q = base + 64 * k + lane;
-                int lo = 0;   // last unit with start <= q: fixed-depth search over at most 640 units
+        for (int step = 512; step > 0; step >>= 1) {
+            const int nxt = u + step;
+            if (nxt < n_units && L.start[nxt] <= q0) u = nxt;
+        }
+        int next_start = L.start[u + 1];
+        int jq = L.j0[u] + (q0 - L.start[u]);   // candidate of pair q
+        int tag = L.tag[u];
+        float4 h = L.home[tag >> 8];
+        // four steps at a time: their candidate loads are in flight together
+        constexpr int kAhead = 4;
+        const int steps = (n_pairs + 63) >> 6;
+        int q = q0;
+        for (int k = 0; k < steps; k += kAhead) {
+            int jj[kAhead], tg[kAhead];
+            float4 hh[kAhead], cc[kAhead];
+            bool lv[kAhead];
 #pragma unroll
-                for (int step = 512; step > 0; step >>= 1) {
-                    const int nxt = lo + step;
-                    if (nxt < n_units && L.start[nxt] <= q) lo = nxt;
+            for (int a = 0; a < kAhead; ++a) {
+                lv[a] = q < q1 && k + a < steps;
+                if (lv[a] && q == next_start) {   // the next unit starts here
+                    ++u;
+                    next_start = L.start[u + 1];
+                    jq = L.j0[u];
+                    tag = L.tag[u];
+                    h = L.home[tag >> 8];
                 }
-                unit[k] = lo;
-            }
-            float4 cand[kLanePairs];
-            int jj[kLanePairs], tg[kLanePairs];
-#pragma unroll
-            for (int k = 0; k < kLanePairs; ++k) {
-                const int q = base + 64 * k + lane;
-                tg[k] = L.tag[unit[k]];
-                jj[k] = L.j0[unit[k]] + (q - L.start[unit[k]]);
-                if (q < n_pairs) cand[k] = p.sorted[jj[k]];
+                jj[a] = jq;
+                tg[a] = tag;
+                hh[a] = h;
+                if (lv[a]) {
+                    ++jq;
+                    ++q;
+                }
             }
 #pragma unroll
-            for (int k = 0; k < kLanePairs; ++k) {
-                const int q = base + 64 * k + lane;
-                const bool live = q < n_pairs;
-                const int hl = tg[k] >> 8, code = tg[k] & 63;
-                const int j = jj[k];
-                const float4 h = L.home[hl];
-                const float4 c = cand[k];
+            for (int a = 0; a < kAhead; ++a)
+                if (lv[a]) cc[a] = p.sorted[jj[a]];
+#pragma unroll
+            for (int a = 0; a < kAhead; ++a) {
+                const int hl = tg[a] >> 8, code = tg[a] & 63;
                 const int s = (int)(tile * 64) + hl;
                 const int bq = one_box ? b0 : __shfl(b, hl, 64);   // all lanes take part in the shuffle
                 bool link = false;
-                if (live) {
+                if (lv[a]) {
+                    const float4 c = cc[a];
+                    const float4 hp = hh[a];
                     const BoxDev &bd = box_of(p, bq);
                     if constexpr (kFP64) {
-                        const double tx = ((double)h.x - (double)c.x) + axis_shift(code & 3, bd.L);
-                        const double ty = ((double)h.y - (double)c.y) + axis_shift((code >> 2) & 3, bd.L);
-                        const double tz = ((double)h.z - (double)c.z) + axis_shift((code >> 4) & 3, bd.L);
+                        const double tx = ((double)hp.x - (double)c.x) + axis_shift(code & 3, bd.L);
+                        const double ty = ((double)hp.y - (double)c.y) + axis_shift((code >> 2) & 3, bd.L);
+                        const double tz = ((double)hp.z - (double)c.z) + axis_shift((code >> 4) & 3, bd.L);
                         const double sxy = tx * tx + ty * ty;
                         const double r2 = sxy + tz * tz;
                         link = strict ? (r2 < bd.l2) : (r2 <= bd.l2);
                     } else {
-                        const float dx = axis_diff(h.x, c.x, code & 3, bd.L32);
-                        const float dy = axis_diff(h.y, c.y, (code >> 2) & 3, bd.L32);
-                        const float dz = axis_diff(h.z, c.z, (code >> 4) & 3, bd.L32);
+                        const float dx = axis_diff(hp.x, c.x, code & 3, bd.L32);
+                        const float dy = axis_diff(hp.y, c.y, (code >> 2) & 3, bd.L32);
+                        const float dz = axis_diff(hp.z, c.z, (code >> 4) & 3, bd.L32);
                         const float rr = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                         if (rr < bd.lo32) link = true;
                         else if (rr > bd.hi32) link = false;
                         else {
                             if (kStats) ++band;
-                            link = link_fp64(h.x, h.y, h.z, c.x, c.y, c.z, bd.L, bd.half, bd.l2, strict);
+                            link = link_fp64(hp.x, hp.y, hp.z, c.x, c.y, c.z, bd.L, bd.half, bd.l2, strict);
                         }
                     }
                     if (kStats) ++tests;
                     if (kStats && link) ++links;
                 }
-                sink.push(p, link, s, j, retries);
+                sink.push(p, link, s, jj[a], retries);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -369,16 +408,21 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
 template <bool kStats>
 __global__ void __launch_bounds__(kBlock) k_union_edges(Plan p)
 {
-    const unsigned n_edges = p.counters->n_edges;
-    const int64_t ne = (int64_t)n_edges < p.max_edges ? (int64_t)n_edges : p.max_edges;
+    const int slice = blockIdx.y;
+    const int64_t cap = p.max_edges / kEdgeSlices;
+    const unsigned fill = p.edge_fill[slice];
+    const int64_t ne = (int64_t)fill < cap ? (int64_t)fill : cap;
+    const int2 *edges = p.edges + slice * cap;
     unsigned retries = 0;
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < ne; k += (int64_t)gridDim.x * kBlock) {
-        const int2 e = p.edges[k];
+        const int2 e = edges[k];
         retries += unite(p.parent, e.x, e.y);
     }
     if (kStats) {
         unsigned long long r = wave_sum_u64((unsigned long long)retries);
         if (lane_id() == 0 && r) atomicAdd(&p.counters->cas_retries, r);
+        // queued pairs, for the statistics
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&p.counters->n_edges, fill);
     }
 }
 
@@ -516,9 +560,8 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
     unsigned long long tests = 0, links = 0, band = 0;
     unsigned retries = 0;
     const int n_items = (int)p.counters->n_items;
-    const int stride = (int)gridDim.x * kWaves;
-
-    for (int it = (int)blockIdx.x * kWaves + wid; it < n_items; it += stride) {
+    const XcdRange xr = xcd_range(n_items, kWaves, wid);   // items come in cell order
+    for (int64_t it = xr.first; it < xr.end; it += xr.stride) {
         const int4 item = p.items[it];
         const int c = __builtin_amdgcn_readfirstlane(item.x);
         const int first = __builtin_amdgcn_readfirstlane(item.y);
@@ -611,7 +654,7 @@ void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
     hipLaunchKernelGGL((k_link_sparse<kFP64, kStats>), dim3((unsigned)p.sparse_blocks), dim3(kBlock), 0, stream, p);
     if (t) t->mark(K_LINK_SPARSE, true, stream);
     if (t) t->mark(K_UNION_EDGES, false, stream);
-    hipLaunchKernelGGL((k_union_edges<kStats>), dim3(4096), dim3(kBlock), 0, stream, p);
+    hipLaunchKernelGGL((k_union_edges<kStats>), dim3(16, kEdgeSlices), dim3(kBlock), 0, stream, p);
     if (t) t->mark(K_UNION_EDGES, true, stream);
     if (t) t->mark(K_LINK_DENSE, false, stream);
     hipLaunchKernelGGL((k_link_dense<kFP64, kStats>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
