@@ -40,13 +40,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 def algorithmic_bytes(kernel: str, n: int, cells: int, nonroot: int, edges: int):
     """Bytes each HBM-bound pass must move at minimum (reads + writes)."""
+    segments = -(-cells // 16384)
     table = {
-        "k_clear": 4 * cells,
+        "k_clear": 4 * segments,
         "k_bucket_hist": 12 * n,                  # xyz in (bucket histogram stays in LDS)
         "k_bucket_scatter": n * (12 + 16 + 4),    # xyz in; staged xyz + index, staging slot out
-        "k_count": n * (16 + 8 + 12),             # staged particle in; cell count RMW; slot, parent, size out
-        "k_cell_scan": 12 * cells,                # counts read twice, starts written once
-        "k_scatter": n * (16 + 4 + 4 + 16 + 8 + 4),  # staged particle, slot, cell start in; sorted, perm, map out
+        "k_seg_hist": 16 * n,                     # staged particle in (segment histogram stays in LDS)
+        "k_seg_scan": 8 * segments,
+        "k_seg_scatter": n * (16 + 16 + 4),       # staged particle in; segment-ordered particle + slot out
+        # segment-ordered particle + slot in; sorted xyz, perm, parent, size, slot map out; cell starts
+        # and occupancy bits out
+        "k_cell_sort": n * (16 + 4 + 16 + 8 + 4 + 4 + 4) + cells * 4 + cells // 8,
         "k_union_edges": 8 * edges,
         "k_flatten": 4 * n + nonroot * (4 + 4 + 8),  # parent in; root out, perm in, two atomics per non-root
         "k_resolve": n * (4 + 8 + 8),             # parent, perm in; label+size per slot out

@@ -61,7 +61,7 @@ typedef enum {
     FOF_ERR_OUT_OF_BOX = 2,    /* a coordinate not finite or outside [0, L) (latched on the device) */
     FOF_ERR_BAD_STATE = 3,     /* calls out of order (link before build, finalize before link) */
     FOF_ERR_WORKSPACE = 4,     /* workspace missing, too small or misaligned */
-    FOF_ERR_DEVICE = 5,        /* a HIP runtime call failed */
+    FOF_ERR_DEVICE = 5,        /* a HIP runtime call failed, or a device-side consistency check */
     FOF_ERR_UNSUPPORTED = 6    /* valid request this build cannot serve (e.g. too many cells) */
 } fof_status;
 
@@ -81,7 +81,10 @@ typedef struct {
                                 per particle. 0 = default (32) */
     int32_t collect_timings; /* 1: record HIP events around every kernel launch on the context's
                                 stream (read with fof_get_kernel_times) */
-    int32_t reserved[5];     /* must be zero */
+    int32_t sort_segment_log2; /* the cell sort counts cells in on-chip memory, 2^k cells per
+                                work-group: k in 6..14; 0 = automatic (about 1.4k particles per
+                                work-group on average). Changes speed only */
+    int32_t reserved[4];     /* must be zero */
 } fof_options;
 
 typedef struct {

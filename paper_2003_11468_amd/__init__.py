@@ -38,7 +38,7 @@ class FoFError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("predicate", ctypes.c_int32), ("strict_less", ctypes.c_int32), ("cell_factor", ctypes.c_double),
                 ("collect_stats", ctypes.c_int32), ("dense_min", ctypes.c_int32), ("collect_timings", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("sort_segment_log2", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -243,8 +243,9 @@ def fof_status_string(status: int) -> str:
 # ------------------------------------------------------ tensor wrapper --
 
 def make_options(predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
-                 stats: bool = False, dense_min: int = 0, timings: bool = False) -> Options:
+                 stats: bool = False, dense_min: int = 0, timings: bool = False, segment_log2: int = 0) -> Options:
     o = fof_default_options()
+    o.sort_segment_log2 = int(segment_log2)
     o.collect_timings = int(timings)
     o.predicate = PREDICATES[predicate]
     o.strict_less = int(strict)
@@ -258,12 +259,13 @@ class FoF:
     """A context plus a workspace tensor, reused across calls of the same shape."""
 
     def __init__(self, predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
-                 stats: bool = False, stream=None, dense_min: int = 0, timings: bool = False):
+                 stats: bool = False, stream=None, dense_min: int = 0, timings: bool = False,
+                 segment_log2: int = 0):
         import torch
 
         self._torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats, dense_min, timings),
+        self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats, dense_min, timings, segment_log2),
                               self.stream.cuda_stream)
         self.ws = None
 

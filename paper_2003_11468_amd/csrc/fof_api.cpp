@@ -45,6 +45,8 @@ struct HostPlan {
     int64_t scan_tiles = 0;
     int64_t n_tiles = 0;
     int32_t bucket_shift = 0, n_buckets = 1;
+    int32_t seg_shift = 0, sub_log2 = 0;
+    int64_t n_segments = 0;
     int64_t fp64_boxes = 0;
     int64_t max_items = 0;
     std::vector<BoxDev> boxes;
@@ -52,7 +54,8 @@ struct HostPlan {
     // workspace layout (byte offsets)
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_rank = 0, o_sorted = 0,
            o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
-           o_stpos = 0, o_wave_roots = 0, o_occ = 0, o_edge_fill = 0, total = 0;
+           o_stpos = 0, o_wave_roots = 0, o_occ = 0, o_edge_fill = 0, o_seg = 0, o_staging2 = 0,
+           o_stage2_k = 0, total = 0;
     int64_t max_edges = 0;
 
     bool same_geometry(const HostPlan &o) const
@@ -140,7 +143,9 @@ bool options_valid(const fof_options &o)
     if (o.collect_stats != 0 && o.collect_stats != 1) return false;
     if (o.dense_min < 0) return false;
     if (o.collect_timings != 0 && o.collect_timings != 1) return false;
-    for (int k = 0; k < 5; ++k)
+    if (o.sort_segment_log2 != 0 && (o.sort_segment_log2 < fof::kSegLog2Min || o.sort_segment_log2 > fof::kSegLog2Max))
+        return false;
+    for (int k = 0; k < 4; ++k)
         if (o.reserved[k] != 0) return false;
     return true;
 }
@@ -230,13 +235,30 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     }
     p.n = offsets[n_boxes];
     p.n_cells = cells;
-    // buckets of consecutive cells for the two-level counting sort: at most 256
+    // Counting sort levels: at most 256 buckets of consecutive cells, each cut
+    // into 2^sub_log2 segments of 2^seg_shift cells (the cells one work-group
+    // counts in LDS). A segment never exceeds a bucket.
+    const int64_t last = cells > 0 ? cells - 1 : 0;
     p.bucket_shift = 0;
-    while (((cells > 0 ? cells - 1 : 0) >> p.bucket_shift) >= 256) ++p.bucket_shift;
-    p.n_buckets = (int32_t)(((cells > 0 ? cells - 1 : 0) >> p.bucket_shift) + 1);
+    while ((last >> p.bucket_shift) >= 256) ++p.bucket_shift;
+    // By default a segment holds about kSegTarget particles on average (its
+    // particles are then placed through LDS), within 2^6 .. 2^14 cells.
+    if (c->opt.sort_segment_log2) {
+        p.seg_shift = c->opt.sort_segment_log2;
+    } else {
+        const double want = (double)fof::kSegTarget * (double)(cells > 0 ? cells : 1) /
+                            (double)(offsets[n_boxes] > 0 ? offsets[n_boxes] : 1);
+        p.seg_shift = fof::kSegLog2Min;
+        while (p.seg_shift < fof::kSegLog2Max && (double)(int64_t(1) << (p.seg_shift + 1)) <= want) ++p.seg_shift;
+    }
+    if (p.seg_shift < p.bucket_shift - fof::kMaxSubLog2) p.seg_shift = p.bucket_shift - fof::kMaxSubLog2;
+    if (p.bucket_shift < p.seg_shift) p.bucket_shift = p.seg_shift;
+    p.sub_log2 = p.bucket_shift - p.seg_shift;
+    p.n_buckets = (int32_t)((last >> p.bucket_shift) + 1);
+    p.n_segments = (last >> p.seg_shift) + 1;
     p.n_tiles = fof::sort_tiles_for(offsets[n_boxes]);
     {
-        const int64_t a = fof::scan_scratch_for(cells + 1);
+        const int64_t a = fof::scan_scratch_for(p.n_segments);
         const int64_t b = fof::scan_scratch_for((int64_t)p.n_buckets * p.n_tiles);
         p.scan_tiles = a > b ? a : b;
     }
@@ -272,7 +294,10 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.o_staging = take(sizeof(float) * 4 * n);
     p.o_stpos = take(sizeof(int32_t) * n);
     p.o_wave_roots = take(sizeof(int32_t) * ((n + 63) / 64));
-    p.o_occ = take(sizeof(uint32_t) * ((size_t)(cells + 1) / 32 + 2));
+    p.o_occ = take(sizeof(uint32_t) * (((size_t)p.n_segments << (p.seg_shift - 5)) + 2));
+    p.o_seg = take(sizeof(int32_t) * (size_t)p.n_segments);
+    p.o_staging2 = take(sizeof(float) * 4 * n);
+    p.o_stage2_k = take(sizeof(int32_t) * n);
     p.total = o;
     *out = std::move(p);
     return FOF_OK;
@@ -335,6 +360,9 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.n_tiles = p.n_tiles;
     d.bucket_shift = p.bucket_shift;
     d.n_buckets = p.n_buckets;
+    d.seg_shift = p.seg_shift;
+    d.sub_log2 = p.sub_log2;
+    d.n_segments = p.n_segments;
     d.dense_min = dense_min_of(c->opt);
     d.dense_blocks = kDenseBlocks;
     d.sparse_blocks = kSparseBlocks;
@@ -359,6 +387,9 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.stpos = at<int32_t>(c->ws, p.o_stpos);
     d.wave_roots = at<int32_t>(c->ws, p.o_wave_roots);
     d.occ = at<uint32_t>(c->ws, p.o_occ);
+    d.seg_end = at<int32_t>(c->ws, p.o_seg);
+    d.staging2 = at<float4>(c->ws, p.o_staging2);
+    d.stage2_k = at<int32_t>(c->ws, p.o_stage2_k);
     d.edge_fill = at<unsigned int>(c->ws, p.o_edge_fill);
     d.n_waves = (p.n + 63) / 64;
     return FOF_OK;
@@ -403,6 +434,7 @@ fof_status read_back(fof_ctx *c, int64_t *h_n_groups, Counters *h_counters)
     if (h_n_groups)
         for (size_t k = 0; k < g.size(); ++k) h_n_groups[k] = (int64_t)g[k];
     if (h_counters) *h_counters = cnt;
+    if (cnt.error & 2u) return FOF_ERR_DEVICE;   // a device-side consistency check failed
     return (cnt.error & 1u) ? FOF_ERR_OUT_OF_BOX : FOF_OK;
 }
 

@@ -33,7 +33,7 @@ struct Counters {
     unsigned long long band_hits;
     unsigned long long cas_retries;
     unsigned long long sparse_tests;   // pair tests of the per-lane (sparse) search
-    unsigned int error;         // bit 0: coordinate outside [0, L) or not finite
+    unsigned int error;         // bit 0: coordinate outside [0, L) or not finite; bit 1: sort inconsistency
     unsigned int n_items;       // work items of the dense link kernel
     unsigned int n_edges;       // linked pairs queued for the union kernel (summed after the search)
     unsigned int pad[5];
@@ -51,6 +51,9 @@ struct Plan {
     int64_t n_tiles;        // input tiles of the bucket pass (2048 particles each)
     int32_t bucket_shift;   // bucket of a cell = cell >> bucket_shift
     int32_t n_buckets;      // at most 256
+    int32_t seg_shift;      // segment of a cell = cell >> seg_shift (6..14; a segment's counts fit in LDS)
+    int32_t sub_log2;       // segments per bucket = 1 << sub_log2 (bucket_shift - seg_shift, at most 10)
+    int64_t n_segments;     // ceil(n_cells / 2^seg_shift)
     int32_t dense_min;      // cells with at least this many particles use the wave kernel
     int32_t dense_blocks;   // grid of the persistent dense link kernel
     int32_t sparse_blocks;  // grid of the persistent sparse link kernel
@@ -62,15 +65,18 @@ struct Plan {
     const BoxDev *boxes;    // [n_boxes] (read only when n_boxes > 1)
     const int64_t *box_p0;  // [n_boxes + 1] particle offsets
 
-    int32_t *cell;          // [n_cells + 1] counts, then exclusive prefix (cell start)
+    int32_t *cell;          // [n_cells + 1] first sorted slot of each cell; cell[n_cells] = n
+    int32_t *seg_end;       // [n_segments] counts, exclusive prefix, then (after the segment pass) end slots
     int32_t *scan_part;     // [scan_tiles] tile sums of every scan level
     int32_t *bucket_hist;   // [n_buckets * n_tiles] counts, then output offsets (bucket-major)
     float4 *staging;        // [n] bucket order: x, y, z, original index (bits); after the link: {label, size}
     int32_t *stpos;         // [n] staging slot of input particle i
-    uint32_t *occ;          // [(n_cells + 1) / 32 + 2] bit c: cell c holds a particle (cell scan)
+    float4 *staging2;       // [n] segment order (cells of a segment together, unordered inside)
+    int32_t *stage2_k;      // [n] staging slot of each segment-order slot
+    uint32_t *occ;          // [n_segments << (seg_shift - 5) + 2] bit c: cell c holds a particle
     int32_t *wave_roots;    // [n_waves] roots among the 64 sorted slots of each wave (resolve)
     int64_t n_waves;
-    int32_t *rank;          // [n] per staging slot: slot inside its cell, after the scatter its sorted slot
+    int32_t *rank;          // [n] sorted slot of each staging slot
     float4 *sorted;         // [n] cell-sorted x, y, z; after the link: {label, size} per sorted slot
     int2 *perm;             // [n] .x original index of sorted particle s, .y group minimum (at roots)
     int32_t *parent;        // [n] union-find forest over sorted indices
@@ -90,12 +96,19 @@ struct Plan {
 int64_t scan_scratch_for(int64_t len);
 int64_t sort_tiles_for(int64_t n);
 
+// Cells per segment of the in-LDS cell sort: 2^kSegLog2Min .. 2^kSegLog2Max;
+// segments per bucket at most 2^kMaxSubLog2.
+constexpr int kSegLog2Min = 6;
+constexpr int kSegLog2Max = 14;
+constexpr int kSegTarget = 1365;      // default: about this many particles per segment
+constexpr int kMaxSubLog2 = 10;
+
 // Capacity of the dense work-item list (fof_link.hip).
 int64_t max_dense_items(int64_t n, int dense_min);
 
 // Kernels in launch order; the ids index per-kernel timings.
 enum KernelId {
-    K_CLEAR, K_BUCKET_HIST, K_BUCKET_SCAN, K_BUCKET_SCATTER, K_COUNT, K_CELL_SCAN, K_SCATTER,
+    K_CLEAR, K_BUCKET_HIST, K_BUCKET_SCAN, K_BUCKET_SCATTER, K_SEG_HIST, K_SEG_SCAN, K_SEG_SCATTER, K_CELL_SORT,
     K_LINK_SPARSE, K_UNION_EDGES, K_LINK_DENSE, K_FLATTEN, K_RESOLVE, K_UNSORT, K_GATHER, K_COUNT_KERNELS
 };
 const char *kernel_name(int k);

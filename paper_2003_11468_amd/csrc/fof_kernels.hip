@@ -3,24 +3,27 @@
 // Pipeline over all boxes at once (every kernel is a flat launch over particles
 // or cells; per-box parameters come from a small descriptor table).
 //
-// The counting sort into cells runs in two levels so that no pass scatters
-// over the whole array. Cells are grouped into at most 256 buckets of
-// consecutive cell indices.
-//   clear          zero the cell counts, group counters and error word
+// The counting sort into cells runs in three levels so that no pass scatters
+// over the whole array and no pass counts cells in global memory. Cells are
+// grouped into at most 256 buckets of consecutive cell indices, and buckets
+// into segments of at most 2^14 cells (a segment's counts fit in LDS).
+//   clear          zero the segment counts, group counters and error word
 //   bucket_hist    per tile of 2048 input particles: validate coordinates,
 //                  bucket histogram in LDS
 //   bucket_scan    exclusive prefix over (bucket, tile) -> where each tile's
 //                  share of each bucket goes
 //   bucket_scatter sort each tile by bucket in LDS and write it out as runs:
 //                  the "staging" order, bucket by bucket
-//   count          in staging order: slot inside the cell (atomic add); the
-//                  atomics of a bucket stay inside its window of cells. Also
-//                  seeds the union-find forest and member counts
-//   cell_scan      exclusive prefix over the cell counts -> cell starts, and
-//                  the dense link work items
-//   scatter        in staging order into cell order (x, y, z as float4) + the
-//                  sorted -> original index map; writes stay in the bucket's
-//                  window of slots
+//   seg_hist       per tile of 2048 staging slots inside one bucket: segment
+//                  histogram in LDS, added to the global segment counts
+//   seg_scan       exclusive prefix over the segment counts
+//   seg_scatter    sort each such tile by segment in LDS and write it out as
+//                  runs: the segment order
+//   cell_sort      one work-group per segment: count its cells in LDS, scan,
+//                  write the cell starts, occupancy bits and dense link work
+//                  items, then place every particle in cell order (x, y, z as
+//                  float4) with its original index, and seed the union-find
+//                  forest
 //   link           (fof_link.hip) cell-pair link search + lock-free union-find
 //   flatten  pointer jumping to the root; group minimum original index
 //            (atomic min) and member count (atomic add) at the root
@@ -50,7 +53,7 @@ constexpr int kMaxBuckets = 256;
 __global__ void __launch_bounds__(kBlock) k_clear(Plan p)
 {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i <= p.n_cells; i += stride) p.cell[i] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < p.n_segments; i += stride) p.seg_end[i] = 0;
     int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < p.n_boxes) p.n_groups[t] = 0;
     if (t < kEdgeSlices) p.edge_fill[t] = 0;
@@ -157,21 +160,6 @@ __global__ void __launch_bounds__(kBlock) k_bucket_scatter(Plan p)
     }
 }
 
-// In staging order: slot of the particle inside its cell. Consecutive staging
-// slots belong to the same bucket, so the atomics stay in a window of cells.
-__global__ void __launch_bounds__(kBlock) k_count(Plan p)
-{
-    const int64_t k = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (k >= p.n) return;
-    const float4 e = p.staging[k];
-    const int i = __float_as_int(e.w);
-    const int b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, i);
-    const int key = particle_cell(box_of(p, b), e.x, e.y, e.z);
-    p.rank[k] = atomicAdd(p.cell + key, 1);
-    p.parent[k] = (int)k;
-    p.gsize[k] = 1;
-}
-
 // ------------------------------------------------------------------ scans --
 // Exclusive prefix sums in place, in tiles of 2048 (8 per thread, 16-byte
 // loads); tile sums are scanned recursively, so no level is a long serial loop.
@@ -210,25 +198,15 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(const int *data, int64_t
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-// kCells: the scan over the cell counts, which also emits one dense link work
-// item {cell, first home particle, box, 0} per 64 particles of every cell with
-// at least dense_min particles.
-template <bool kCells>
-__global__ void __launch_bounds__(kBlock) k_scan_apply(ScanArgs a, Plan p)
+__global__ void __launch_bounds__(kBlock) k_scan_apply(ScanArgs a)
 {
     __shared__ int lds[kBlock / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
     load8(a.data, base, a.len, v);
-    int s = 0, chunks = 0;
+    int s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        s += v[k];
-        if (kCells) {
-            const bool dense = base + k < p.n_cells && v[k] >= p.dense_min && v[k] > 0;
-            chunks += dense ? (v[k] + 63) >> 6 : 0;
-        }
-    }
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     int total;
     const int start = block_excl_scan<kBlock>(s, lds, &total) + (a.part ? a.part[blockIdx.x] : 0);
     int o[kScanItems];
@@ -246,46 +224,294 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(ScanArgs a, Plan p)
         for (int k = 0; k < kScanItems; ++k)
             if (base + k < a.len) a.data[base + k] = o[k];
     }
-    if (kCells) {
-        // occupancy bits: the 8 cells of 4 consecutive threads form one word
-        unsigned bits = 0;
+}
+
+// ---------------------------------------------------------- segment pass --
+
+// Cell of a staged particle (x, y, z, original index as bits).
+__device__ __forceinline__ int staged_cell(const Plan &p, const float4 &v)
+{
+    const int b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, __float_as_int(v.w));
+    return particle_cell(box_of(p, b), v.x, v.y, v.z);
+}
+
+// Tiles of the segment pass: each bucket's window of staging slots is cut
+// into tiles of kSortTile, so no tile straddles buckets. Work-group g takes
+// tile g of that list (the list has at most n_tiles + n_buckets entries).
+// Returns the bucket, or -1 for a work-group past the last tile.
+__device__ __forceinline__ int seg_tile(const Plan &p, int *info, int *lds, int &lo, int &hi)
+{
+    const int t = threadIdx.x;   // one bucket per thread (kBlock == kMaxBuckets)
+    int start = 0, end = 0, tiles = 0;
+    if (t < p.n_buckets) {
+        start = p.bucket_hist[(int64_t)t * p.n_tiles];
+        end = t + 1 < p.n_buckets ? p.bucket_hist[(int64_t)(t + 1) * p.n_tiles] : (int)p.n;
+        tiles = (end - start + kSortTile - 1) / kSortTile;
+    }
+    if (t == 0) info[0] = -1;
+    int total;
+    const int first = block_excl_scan<kBlock>(tiles, lds, &total);   // synchronises after info[0] = -1
+    const int g = (int)blockIdx.x;
+    if (g >= first && g < first + tiles) {
+        info[0] = t;
+        info[1] = start + (g - first) * kSortTile;
+        info[2] = min(end, start + (g - first + 1) * kSortTile);
+    }
+    __syncthreads();
+    lo = info[1];
+    hi = info[2];
+    return info[0];
+}
+
+constexpr int kMaxSubs = 1 << kMaxSubLog2;
+
+// Segment histogram of one tile (LDS), added to the global segment counts.
+__global__ void __launch_bounds__(kBlock) k_seg_hist(Plan p)
+{
+    __shared__ int cnt[kMaxSubs];
+    __shared__ int info[3], lds[kBlock / 64];
+    int lo, hi;
+    const int b = seg_tile(p, info, lds, lo, hi);
+    if (b < 0) return;
+    const int subs = 1 << p.sub_log2;
+    const int seg0 = b << p.sub_log2;
+    for (int s = threadIdx.x; s < subs; s += kBlock) cnt[s] = 0;
+    __syncthreads();
+    for (int k = lo + (int)threadIdx.x; k < hi; k += kBlock)
+        atomicAdd(&cnt[(staged_cell(p, p.staging[k]) >> p.seg_shift) - seg0], 1);
+    __syncthreads();
+    for (int s = threadIdx.x; s < subs; s += kBlock)
+        if (cnt[s]) atomicAdd(p.seg_end + seg0 + s, cnt[s]);
+}
+
+// Sorts one tile by segment in LDS and appends each segment's run at that
+// segment's cursor (seg_end: start before, end after this pass).
+__global__ void __launch_bounds__(kBlock) k_seg_scatter(Plan p)
+{
+    __shared__ float4 stage[kSortTile];
+    __shared__ int stage_k[kSortTile];
+    __shared__ unsigned short stage_s[kSortTile];
+    __shared__ int cnt[kMaxSubs], first[kMaxSubs], dst0[kMaxSubs];
+    __shared__ int info[3], lds[kBlock / 64];
+    int lo, hi;
+    const int b = seg_tile(p, info, lds, lo, hi);
+    if (b < 0) return;
+    const int subs = 1 << p.sub_log2;
+    const int seg0 = b << p.sub_log2;
+    for (int s = threadIdx.x; s < subs; s += kBlock) cnt[s] = 0;
+    __syncthreads();
+    float4 v[kSortItems];
+    int sb[kSortItems], rk[kSortItems];
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) bits |= (v[k] > 0 ? 1u : 0u) << k;
-        const int lane = lane_id();
-        const unsigned b1 = __shfl_down(bits, 1, 64), b2 = __shfl_down(bits, 2, 64), b3 = __shfl_down(bits, 3, 64);
-        if ((lane & 3) == 0 && base < a.len) p.occ[base >> 5] = bits | (b1 << 8) | (b2 << 16) | (b3 << 24);
-        // one atomic per wave reserves the item slots
-        const int incl = wave_incl_scan(chunks);
-        const int wave_total = __shfl(incl, 63, 64);
-        int slot = 0;
-        if (lane_id() == 63 && wave_total > 0) slot = (int)atomicAdd(&p.counters->n_items, (unsigned)wave_total);
-        slot = __shfl(slot, 63, 64) + incl - chunks;
-        if (chunks) {
-#pragma unroll 1
-            for (int k = 0; k < kScanItems; ++k) {
-                const bool dense = base + k < p.n_cells && v[k] >= p.dense_min && v[k] > 0;
-                if (!dense) continue;
-                const int first_p = o[k];
-                const int b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, first_p);
-                for (int q = 0; q < v[k]; q += 64) p.items[slot++] = make_int4((int)(base + k), first_p + q, b, 0);
-            }
+    for (int q = 0; q < kSortItems; ++q) {
+        const int k = lo + q * kBlock + (int)threadIdx.x;
+        sb[q] = -1;
+        if (k < hi) {
+            v[q] = p.staging[k];
+            sb[q] = (staged_cell(p, v[q]) >> p.seg_shift) - seg0;
+            rk[q] = atomicAdd(&cnt[sb[q]], 1);
         }
+    }
+    __syncthreads();
+    {
+        // exclusive prefix over the segments: thread t owns `per` consecutive ones
+        const int per = subs >= kBlock ? subs / kBlock : 1;
+        const int s0 = (int)threadIdx.x * per;
+        int c[kMaxSubs / kBlock];
+        int sum = 0;
+#pragma unroll
+        for (int q = 0; q < kMaxSubs / kBlock; ++q) {
+            c[q] = (q < per && s0 + q < subs) ? cnt[s0 + q] : 0;
+            sum += c[q];
+        }
+        int total;
+        int run = block_excl_scan<kBlock>(sum, lds, &total);
+#pragma unroll
+        for (int q = 0; q < kMaxSubs / kBlock; ++q)
+            if (q < per && s0 + q < subs) {
+                first[s0 + q] = run;
+                dst0[s0 + q] = c[q] ? atomicAdd(p.seg_end + seg0 + s0 + q, c[q]) : 0;
+                run += c[q];
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSortItems; ++q)
+        if (sb[q] >= 0) {
+            const int at = first[sb[q]] + rk[q];
+            stage[at] = v[q];
+            stage_k[at] = lo + q * kBlock + (int)threadIdx.x;
+            stage_s[at] = (unsigned short)sb[q];
+        }
+    __syncthreads();
+    const int count = hi - lo;
+    for (int j = threadIdx.x; j < count; j += kBlock) {
+        const int s = stage_s[j];
+        const int dst = dst0[s] + (j - first[s]);
+        p.staging2[dst] = stage[j];
+        p.stage2_k[dst] = stage_k[j];
     }
 }
 
-// In staging order into cell order; rank[k] becomes the sorted slot of staging slot k.
-__global__ void __launch_bounds__(kBlock) k_scatter(Plan p)
+// ------------------------------------------------------------- cell sort --
+
+constexpr int kSegBlock = 512;
+constexpr int kSegWaves = kSegBlock / 64;
+constexpr int kSegUnroll = 4;            // particles in flight per thread
+constexpr int kOrderCap = 4096;          // segments up to this many particles are placed through LDS
+
+// LDS slot of cell c: one pad word per 32 cells, so a thread walking 32
+// consecutive cells and its neighbour lanes hit different banks.
+__device__ __forceinline__ int pad_idx(int c) { return c + (c >> 5); }
+
+// One work-group per segment of 2^seg_shift consecutive cells, whose P
+// particles own sorted slots [a, a + P) (seg_end).
+//  1. count the cells in LDS;
+//  2. exclusive prefix: thread t owns a run of consecutive cells (one block
+//     scan, no per-step wave scans);
+//  3. cell starts, occupancy bits (one 64-bit word per wave step) and dense
+//     link work items {cell, first home particle, box, 0}, one per 64
+//     particles of every cell with at least dense_min particles;
+//  4. place the particles: the LDS cursors give each its slot; up to
+//     kOrderCap particles the slot order is kept in LDS and the outputs are
+//     written in slot order (coalesced), otherwise written directly.
+// A slot outside [0, P) cannot happen with consistent counts; it is latched
+// as error bit 1 instead of being written.
+__global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
 {
-    const int64_t k = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (k >= p.n) return;
-    const float4 e = p.staging[k];
-    const int i = __float_as_int(e.w);
-    const int b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, i);
-    const int key = particle_cell(box_of(p, b), e.x, e.y, e.z);
-    const int dst = p.cell[key] + p.rank[k];
-    p.sorted[dst] = make_float4(e.x, e.y, e.z, 0.0f);
-    p.perm[dst] = make_int2(i, i);
-    p.rank[k] = dst;
+    __shared__ int cnt[(1 << kSegLog2Max) + (1 << (kSegLog2Max - 5)) + 1];
+    __shared__ unsigned short order[kOrderCap];
+    __shared__ int lds[kSegWaves];
+    const int j = (int)blockIdx.x;
+    const int seg_cells = 1 << p.seg_shift;
+    const int cell0 = j << p.seg_shift;
+    const int a = j ? p.seg_end[j - 1] : 0;
+    const int e = p.seg_end[j];
+    const int P = e - a;
+    const int tid = (int)threadIdx.x;
+    const int sentinel = pad_idx(seg_cells);
+    for (int c = tid; c <= sentinel; c += kSegBlock) cnt[c] = 0;
+    __syncthreads();
+
+    // 1. counts
+    for (int k0 = a + tid; k0 < e; k0 += kSegUnroll * kSegBlock) {
+        float4 v[kSegUnroll];
+#pragma unroll
+        for (int q = 0; q < kSegUnroll; ++q)
+            if (k0 + q * kSegBlock < e) v[q] = p.staging2[k0 + q * kSegBlock];
+#pragma unroll
+        for (int q = 0; q < kSegUnroll; ++q)
+            if (k0 + q * kSegBlock < e) atomicAdd(&cnt[pad_idx(staged_cell(p, v[q]) - cell0)], 1);
+    }
+    __syncthreads();
+
+    // 2. exclusive prefix (local slots)
+    {
+        const int per = seg_cells >= kSegBlock ? seg_cells / kSegBlock : 1;
+        const int c0 = tid * per;
+        const bool owns = c0 < seg_cells;
+        int sum = 0;
+        if (owns)
+            for (int q = 0; q < per; ++q) sum += cnt[pad_idx(c0 + q)];
+        int total;
+        int run = block_excl_scan<kSegBlock>(sum, lds, &total);
+        if (owns)
+            for (int q = 0; q < per; ++q) {
+                const int i = pad_idx(c0 + q);
+                const int v = cnt[i];
+                cnt[i] = run;
+                run += v;
+            }
+        if (tid == 0) cnt[sentinel] = P;
+    }
+    __syncthreads();
+
+    // 3. cell starts, occupancy bits, dense work items (64 consecutive cells per wave step)
+    {
+        const int lane = lane_id();
+        const int64_t n_cells = p.n_cells;
+        for (int c = tid; c < seg_cells; c += kSegBlock) {
+            const int st = cnt[pad_idx(c)];
+            const int v = cnt[pad_idx(c + 1)] - st;
+            const int start = a + st;
+            const int gc = cell0 + c;
+            if (gc <= n_cells) p.cell[gc] = start;          // cell n_cells (the end) has no particle: start = n
+            const unsigned long long bits = __ballot(v > 0);
+            if (lane == 0) *reinterpret_cast<unsigned long long *>(p.occ + ((cell0 + c) >> 5)) = bits;
+            const int chunks = (v >= p.dense_min && v > 0) ? (v + 63) >> 6 : 0;
+            if (__ballot(chunks > 0)) {
+                const int cincl = wave_incl_scan(chunks);
+                const int wave_items = __shfl(cincl, 63, 64);
+                int slot = 0;
+                if (lane == 63) slot = (int)atomicAdd(&p.counters->n_items, (unsigned)wave_items);
+                slot = __shfl(slot, 63, 64) + cincl - chunks;
+                if (chunks) {
+                    const int bx = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, start);
+                    for (int q = 0; q < v; q += 64, ++slot)
+                        if (slot < p.max_items) p.items[slot] = make_int4(gc, start + q, bx, 0);
+                }
+            }
+        }
+        // the end marker when the cells fill the last segment exactly
+        if (j + 1 == (int)gridDim.x && tid == 0 && (n_cells & (seg_cells - 1)) == 0) p.cell[n_cells] = e;
+    }
+    __syncthreads();
+
+    // 4. placement
+    const bool through_lds = P <= kOrderCap;
+    bool bad = false;
+    for (int k0 = a + tid; k0 < e; k0 += kSegUnroll * kSegBlock) {
+        float4 v[kSegUnroll];
+#pragma unroll
+        for (int q = 0; q < kSegUnroll; ++q)
+            if (k0 + q * kSegBlock < e) v[q] = p.staging2[k0 + q * kSegBlock];
+#pragma unroll
+        for (int q = 0; q < kSegUnroll; ++q) {
+            const int k = k0 + q * kSegBlock;
+            if (k >= e) continue;
+            const int local = atomicAdd(&cnt[pad_idx(staged_cell(p, v[q]) - cell0)], 1);
+            if ((unsigned)local >= (unsigned)P) {
+                bad = true;
+                continue;
+            }
+            if (through_lds) {
+                order[local] = (unsigned short)(k - a);
+            } else {
+                const int dst = a + local;
+                const int i = __float_as_int(v[q].w);
+                p.sorted[dst] = make_float4(v[q].x, v[q].y, v[q].z, 0.0f);
+                p.perm[dst] = make_int2(i, i);
+                p.parent[dst] = dst;
+                p.gsize[dst] = 1;
+                p.rank[p.stage2_k[k]] = dst;
+            }
+        }
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(&p.counters->error, 2u);
+    if (!through_lds) return;
+    __syncthreads();
+    for (int d0 = tid; d0 < P; d0 += kSegUnroll * kSegBlock) {
+        float4 v[kSegUnroll];
+        int from[kSegUnroll], k_of[kSegUnroll];
+#pragma unroll
+        for (int q = 0; q < kSegUnroll; ++q)
+            if (d0 + q * kSegBlock < P) {
+                from[q] = a + order[d0 + q * kSegBlock];
+                v[q] = p.staging2[from[q]];
+                k_of[q] = p.stage2_k[from[q]];
+            }
+#pragma unroll
+        for (int q = 0; q < kSegUnroll; ++q)
+            if (d0 + q * kSegBlock < P) {
+                const int dst = a + d0 + q * kSegBlock;
+                const int i = __float_as_int(v[q].w);
+                p.sorted[dst] = make_float4(v[q].x, v[q].y, v[q].z, 0.0f);
+                p.perm[dst] = make_int2(i, i);
+                p.parent[dst] = dst;
+                p.gsize[dst] = 1;
+                p.rank[k_of[q]] = dst;
+            }
+    }
 }
 
 // Consecutive sorted particles mostly share their root, so the root updates
@@ -346,26 +572,43 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Plan p)
 }
 
 // n_groups[box] += sum of wave_roots over the waves of the box (a wave belongs
-// to the box of its first particle). One block per box, strided.
+// to the box of its first particle). Each work-group sums a contiguous run of
+// kGroupRun entries; boxes are contiguous in the wave index, so a single box
+// takes one atomic per work-group and several boxes one per box per wave.
+constexpr int kGroupItems = 4;
+constexpr int kGroupRun = kBlock * kGroupItems;
+
 __global__ void __launch_bounds__(kBlock) k_group_count(Plan p)
 {
     __shared__ unsigned long long part[kBlock / 64];
-    for (int b = blockIdx.x; b < p.n_boxes; b += gridDim.x) {
-        const int64_t p0 = p.n_boxes == 1 ? 0 : p.box_p0[b];
-        const int64_t p1 = p.n_boxes == 1 ? p.n : p.box_p0[b + 1];
-        // waves whose first particle lies in [p0, p1)
-        const int64_t w0 = (p0 + 63) >> 6, w1 = (p1 + 63) >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kGroupRun;
+    if (p.n_boxes == 1) {
         unsigned long long sum = 0;
-        for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock) sum += (unsigned)p.wave_roots[w];
+#pragma unroll
+        for (int k = 0; k < kGroupItems; ++k) {
+            const int64_t w = base + k * kBlock + threadIdx.x;
+            if (w < p.n_waves) sum += (unsigned)p.wave_roots[w];
+        }
         sum = wave_sum_u64(sum);
         if (lane_id() == 0) part[threadIdx.x >> 6] = sum;
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned long long t = 0;
             for (int k = 0; k < kBlock / 64; ++k) t += part[k];
-            if (t) atomicAdd(p.n_groups + b, t);
+            if (t) atomicAdd(p.n_groups, t);
         }
-        __syncthreads();
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < kGroupItems; ++k) {
+        const int64_t w = base + k * kBlock + threadIdx.x;
+        int key = -1;
+        unsigned long long v = 0;
+        if (w < p.n_waves) {
+            v = (unsigned)p.wave_roots[w];
+            if (v) key = find_box(p.box_p0, p.n_boxes, w << 6);
+        }
+        wave_add_by_key(p.n_groups, key, v);
     }
 }
 
@@ -397,17 +640,16 @@ inline int64_t grid_tiles(int64_t n) { return (n + kBlock - 1) / kBlock; }
 
 // Exclusive scan of data[0, len) in place; `scratch` holds the tile sums of
 // every level (scan_scratch_for(len) ints).
-void scan_exclusive(int *data, int64_t len, int *scratch, const Plan &p, bool cells, hipStream_t stream)
+void scan_exclusive(int *data, int64_t len, int *scratch, hipStream_t stream)
 {
     const int64_t tiles = (len + kScanTile - 1) / kScanTile;
     ScanArgs a{data, len, nullptr};
     if (tiles > 1) {
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, stream, data, len, scratch);
-        scan_exclusive(scratch, tiles, scratch + tiles, p, false, stream);
+        scan_exclusive(scratch, tiles, scratch + tiles, stream);
         a.part = scratch;
     }
-    if (cells) hipLaunchKernelGGL((k_scan_apply<true>), dim3((unsigned)tiles), dim3(kBlock), 0, stream, a, p);
-    else hipLaunchKernelGGL((k_scan_apply<false>), dim3((unsigned)tiles), dim3(kBlock), 0, stream, a, p);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(kBlock), 0, stream, a);
 }
 
 }  // namespace
@@ -423,7 +665,8 @@ void scan_exclusive(int *data, int64_t len, int *scratch, const Plan &p, bool ce
 const char *kernel_name(int k)
 {
     static const char *names[K_COUNT_KERNELS] = {
-        "k_clear", "k_bucket_hist", "k_bucket_scan", "k_bucket_scatter", "k_count", "k_cell_scan", "k_scatter",
+        "k_clear", "k_bucket_hist", "k_bucket_scan", "k_bucket_scatter", "k_seg_hist", "k_seg_scan", "k_seg_scatter",
+        "k_cell_sort",
         "k_link_sparse", "k_union_edges", "k_link_dense", "k_flatten", "k_resolve", "k_unsort", "k_gather"};
     return (k >= 0 && k < K_COUNT_KERNELS) ? names[k] : "?";
 }
@@ -442,7 +685,8 @@ int64_t sort_tiles_for(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
 hipError_t launch_clear(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
-    int64_t work = p.n_cells + 1 > p.n_boxes ? p.n_cells + 1 : p.n_boxes;
+    int64_t work = p.n_segments > p.n_boxes ? p.n_segments : p.n_boxes;
+    if (work < kEdgeSlices) work = kEdgeSlices;
     unsigned g = grid_for(work);
     if (g > 65536u) g = 65536u;
     FOF_TIMED(K_CLEAR, hipLaunchKernelGGL(k_clear, dim3(g), dim3(kBlock), 0, stream, p));
@@ -451,20 +695,20 @@ hipError_t launch_clear(const Plan &p, hipStream_t stream, KernelTimer *t)
 
 hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
+    const unsigned seg_tiles = (unsigned)(p.n_tiles + p.n_buckets);
     if (p.n > 0) {
         const unsigned tiles = (unsigned)p.n_tiles;
         FOF_TIMED(K_BUCKET_HIST, hipLaunchKernelGGL(k_bucket_hist, dim3(tiles), dim3(kBlock), 0, stream, p));
-        FOF_TIMED(K_BUCKET_SCAN,
-                  scan_exclusive(p.bucket_hist, (int64_t)p.n_buckets * p.n_tiles, p.scan_part, p, false, stream));
+        FOF_TIMED(K_BUCKET_SCAN, scan_exclusive(p.bucket_hist, (int64_t)p.n_buckets * p.n_tiles, p.scan_part, stream));
         FOF_TIMED(K_BUCKET_SCATTER,
                   hipLaunchKernelGGL(k_bucket_scatter, dim3(tiles), dim3(kBlock), 0, stream, p));
-        FOF_TIMED(K_COUNT,
-                  hipLaunchKernelGGL(k_count, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p));
+        FOF_TIMED(K_SEG_HIST, hipLaunchKernelGGL(k_seg_hist, dim3(seg_tiles), dim3(kBlock), 0, stream, p));
     }
-    FOF_TIMED(K_CELL_SCAN, scan_exclusive(p.cell, p.n_cells + 1, p.scan_part, p, true, stream));
+    FOF_TIMED(K_SEG_SCAN, scan_exclusive(p.seg_end, p.n_segments, p.scan_part, stream));
     if (p.n > 0)
-        FOF_TIMED(K_SCATTER,
-                  hipLaunchKernelGGL(k_scatter, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p));
+        FOF_TIMED(K_SEG_SCATTER, hipLaunchKernelGGL(k_seg_scatter, dim3(seg_tiles), dim3(kBlock), 0, stream, p));
+    FOF_TIMED(K_CELL_SORT,
+              hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)p.n_segments), dim3(kSegBlock), 0, stream, p));
     return hipGetLastError();
 }
 
@@ -474,7 +718,8 @@ hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t)
     FOF_TIMED(K_FLATTEN, hipLaunchKernelGGL(k_flatten, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
     FOF_TIMED(K_RESOLVE, {
         hipLaunchKernelGGL(k_resolve, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p);
-        hipLaunchKernelGGL(k_group_count, dim3((unsigned)min(p.n_boxes, 4096)), dim3(kBlock), 0, stream, p);
+        hipLaunchKernelGGL(k_group_count, dim3((unsigned)((p.n_waves + kGroupRun - 1) / kGroupRun)), dim3(kBlock), 0,
+                           stream, p);
     });
     FOF_TIMED(K_UNSORT, hipLaunchKernelGGL(k_unsort, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p));
     FOF_TIMED(K_GATHER, hipLaunchKernelGGL(k_gather, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));

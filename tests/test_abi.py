@@ -18,7 +18,7 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     lib = fof.load_library()
     names = declared_functions()
-    assert len(names) >= 14
+    assert len(names) >= 15
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(names) == sorted(fof.EXPORTS)
@@ -40,7 +40,8 @@ def _ctx(**kw):
 
 
 def test_create_rejects_bad_options():
-    for kw in (dict(cell_factor=0.5), dict(cell_factor=float("inf"))):
+    for kw in (dict(cell_factor=0.5), dict(cell_factor=float("inf")), dict(segment_log2=5), dict(segment_log2=15),
+               dict(segment_log2=-1)):
         with pytest.raises(fof.FoFError) as e:
             _ctx(**kw)
         assert e.value.status == fof.FOF_ERR_INVALID_ARG
@@ -153,7 +154,7 @@ def test_kernel_times_need_the_option():
         assert e.value.status == fof.FOF_ERR_BAD_STATE
     finally:
         fof.fof_destroy(ctx)
-    names = [fof.fof_kernel_name(k) for k in range(14)]
+    names = [fof.fof_kernel_name(k) for k in range(15)]
     assert names[0] == "k_clear" and "k_link_dense" in names and "?" not in names
     assert fof.fof_kernel_name(99) == "?"
 

@@ -21,8 +21,8 @@ PREDICATES = ["fp32_filter", "fp64"]
 
 
 def gpu_run(pos, offsets, box, lx, predicate="fp32_filter", strict=False, cell_factor=0.0, stats=False,
-            dense_min=0):
-    f = fof.FoF(predicate, strict, cell_factor, stats, dense_min=dense_min)
+            dense_min=0, segment_log2=0):
+    f = fof.FoF(predicate, strict, cell_factor, stats, dense_min=dense_min, segment_log2=segment_log2)
     try:
         p = torch.from_numpy(np.ascontiguousarray(pos, dtype=np.float32)).cuda()
         label, size, ng = f.run(p, offsets, box, lx)
@@ -32,9 +32,11 @@ def gpu_run(pos, offsets, box, lx, predicate="fp32_filter", strict=False, cell_f
         f.close()
 
 
-def assert_single(pos, lx, box=1.0, strict=False, predicate="fp32_filter", cell_factor=0.0, dense_min=0):
+def assert_single(pos, lx, box=1.0, strict=False, predicate="fp32_filter", cell_factor=0.0, dense_min=0,
+                  segment_log2=0):
     ref = oracle.fof(pos, lx, box, strict=strict)
-    lab, size, ng, _ = gpu_run(pos, [0, len(pos)], box, lx, predicate, strict, cell_factor, dense_min=dense_min)
+    lab, size, ng, _ = gpu_run(pos, [0, len(pos)], box, lx, predicate, strict, cell_factor, dense_min=dense_min,
+                               segment_log2=segment_log2)
     assert np.array_equal(lab, ref[0])
     assert np.array_equal(size, ref[1])
     assert int(ng[0]) == ref[2]
@@ -172,6 +174,26 @@ def test_kernel_paths_on_hand_cases(dense_min):
     for predicate in PREDICATES:
         lab, size, ng, _ = gpu_run(w.pos, w.offsets, w.box, w.lx, predicate, dense_min=dense_min)
         assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and np.array_equal(ng, ref[2])
+
+
+# The cell sort counts 2^k cells per work-group: small k gives many segments
+# per bucket, k = 14 one segment per bucket; 16^3 and 32^3 cells fill their
+# last segment exactly (the end marker comes from the last work-group).
+@pytest.mark.parametrize("segment_log2", [6, 7, 9, 12, 14])
+def test_cell_sort_segments(segment_log2):
+    n = 120000
+    pos = synth.clustered(n, 23, 0, 0.7)
+    for b, cf in ((0.2, 0.0), (0.4, 1.0), (0.2, 3.0)):
+        assert_single(pos, synth.linking_length(b, n), cell_factor=cf, segment_log2=segment_log2)
+    for nside in (16, 32):
+        u = synth.uniform(nside ** 3, 29)
+        lx = synth.linking_length(0.9, nside ** 3)
+        assert oracle.cells_per_axis(nside ** 3, lx) == nside
+        assert_single(u, lx, segment_log2=segment_log2)
+    w = synth.make("batched256", n_boxes=20, size_scale=0.05)
+    ref = oracle.fof_boxes(w.pos, w.offsets, w.box, w.lx)
+    lab, size, ng, _ = gpu_run(w.pos, w.offsets, w.box, w.lx, segment_log2=segment_log2)
+    assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and np.array_equal(ng, ref[2])
 
 
 def test_uniform32k_and_strict():
@@ -312,7 +334,7 @@ def test_kernel_times_cover_every_kernel():
         for _ in range(3):
             f.run(pos, [0, n], 1.0, synth.linking_length(0.2, n))
         kt = f.kernel_times()
-        assert set(kt) == {fof.fof_kernel_name(k) for k in range(14)}
+        assert set(kt) == {fof.fof_kernel_name(k) for k in range(15)}
         for name, (ms, launches) in kt.items():
             assert launches == 3 and ms > 0.0, name
         assert all(c == 0 for _, c in f.kernel_times().values())   # the record was cleared
