@@ -53,8 +53,7 @@ def algorithmic_bytes(kernel: str, n: int, cells: int, nonroot: int, edges: int)
         "k_cell_sort": n * (16 + 4 + 16 + 8 + 4 + 4 + 4) + cells * 4 + cells // 8,
         "k_union_edges": 8 * edges,
         "k_flatten": 4 * n + nonroot * (4 + 4 + 8),  # parent in; root out, perm in, two atomics per non-root
-        "k_resolve": n * (4 + 8 + 8),             # parent, perm in; label+size per slot out
-        "k_unsort": n * (4 + 8 + 8),              # slot map, label+size in; label+size per staging slot out
+        "k_resolve": n * (4 + 8 + 4 + 8),         # parent, perm, staging slot in; label+size per staging slot out
         "k_gather": n * (4 + 8 + 8),              # staging slot, label+size in; label, size out
     }
     return table.get(kernel)
@@ -78,6 +77,10 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (a known-size kernel whose "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE calibrates the counters)")
+    ap.add_argument("--ingest-counters", metavar="DIR", default=None,
+                    help="no GPU work: read rocprofv3 CSV output under DIR/{trace,fetch,write} (kernel trace, "
+                         "FETCH_SIZE and WRITE_SIZE runs of the same command, with --copy-calibration), write "
+                         "profiles/traffic.json and print a markdown summary")
     return ap.parse_args()
 
 
@@ -105,6 +108,68 @@ def measured_traffic(kernel: str):
         return None
     k = d.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def _kernel_key(name: str) -> str:
+    """`void fof::(anonymous namespace)::k_link_sparse<false, false>(fof::Plan)` -> `k_link_sparse<false, false>`."""
+    head = name.split("(fof::")[0].split("(int const*")[0]
+    head = head.rsplit("::", 1)[-1] if "::" in head.split("<")[0] else head
+    return head.strip()
+
+
+def ingest_counters(d: str) -> str:
+    """Per-kernel HBM traffic from a rocprofv3 FETCH_SIZE run and a WRITE_SIZE
+    run (KiB per dispatch), each scaled by what the counter reads for a copy
+    of known size in the same run; average durations from the kernel-trace
+    run. Writes TRAFFIC_FILE and returns a markdown summary."""
+    import csv
+    import collections
+
+    def rows(sub, fname):
+        return list(csv.DictReader(open(os.path.join(d, sub, fname))))
+
+    vals = {}
+    for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        per = collections.defaultdict(list)
+        for r in rows(sub, "run_counter_collection.csv"):
+            if r["Counter_Name"] == ctr:
+                per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        vals[ctr] = per
+    copies = vals["FETCH_SIZE"].get("__amd_rocclr_copyBuffer", [])
+    fills = [v for k, vs in vals["WRITE_SIZE"].items() if "FillFunctor" in k for v in vs]
+    if not copies or not fills:
+        raise SystemExit("no calibration copy/fill in the counter runs (use --copy-calibration)")
+    cal_kib = max(fills)                       # the fill writes exactly the calibration buffer
+    fetch_factor = cal_kib / max(copies)       # the copy reads it once
+    write_factor = cal_kib / max(fills)
+    stats = {}
+    for r in rows("trace", "run_kernel_stats.csv"):
+        stats[r["Name"]] = (int(r["Calls"]), float(r["AverageNs"]))
+    kernels = {}
+    lines = ["| kernel | calls | avg us | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB (scaled) | GB/s |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for name, (calls, avg_ns) in sorted(stats.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+        f = vals["FETCH_SIZE"].get(name)
+        w = vals["WRITE_SIZE"].get(name)
+        if not f or not w or "fof::" not in name:
+            continue
+        fk, wk = statistics.mean(f), statistics.mean(w)
+        b = (fk * fetch_factor + wk * write_factor) * 1024.0
+        key = _kernel_key(name)
+        lines.append(f"| `{key}` | {calls} | {avg_ns / 1e3:.1f} | {fk:.0f} | {wk:.0f} | {b / 1e6:.1f} | "
+                     f"{b / avg_ns:.0f} |")
+        base = key.split("<")[0]
+        # the variant launched most often (the timed one) names the kernel
+        if base not in kernels or calls > kernels[base]["calls"]:
+            kernels[base] = {"calls": calls, "avg_ns": avg_ns, "bytes_per_launch": b, "variant": key}
+    out = {"source_sha": source_sha(), "fetch_factor": fetch_factor, "write_factor": write_factor,
+           "calibration_kib": cal_kib, "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    head = [f"Calibration: a {cal_kib / 1024:.0f} MiB fill reads WRITE_SIZE {max(fills):.0f} KiB "
+            f"(factor {write_factor:.3f}); a copy of it reads FETCH_SIZE {max(copies):.0f} KiB "
+            f"(factor {fetch_factor:.3f}).", ""]
+    return "\n".join(head + lines) + "\n"
 
 
 def choose(torch, tune, pos, w, predicate, args):
@@ -156,6 +221,9 @@ def cpu_baseline(w):
 
 def main():
     args = parse()
+    if args.ingest_counters:
+        print(ingest_counters(args.ingest_counters), end="")
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)

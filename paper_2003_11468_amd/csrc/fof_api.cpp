@@ -52,7 +52,7 @@ struct HostPlan {
     std::vector<BoxDev> boxes;
     std::vector<int64_t> p0;
     // workspace layout (byte offsets)
-    size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_rank = 0, o_sorted = 0,
+    size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_kmap = 0, o_sorted = 0,
            o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
            o_stpos = 0, o_wave_roots = 0, o_occ = 0, o_edge_fill = 0, o_seg = 0, o_staging2 = 0,
            o_stage2_k = 0, total = 0;
@@ -277,7 +277,7 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.o_groups = take(sizeof(unsigned long long) * (size_t)n_boxes);
     p.o_cell = take(sizeof(int32_t) * ((size_t)cells + 1));
     p.o_part = take(sizeof(int32_t) * (size_t)p.scan_tiles);
-    p.o_rank = take(sizeof(int32_t) * n);
+    p.o_kmap = take(sizeof(int32_t) * n);
     p.o_sorted = take(sizeof(float) * 4 * n);
     p.o_perm = take(sizeof(int32_t) * 2 * n);
     p.o_parent = take(sizeof(int32_t) * n);
@@ -375,7 +375,7 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.n_groups = at<unsigned long long>(c->ws, p.o_groups);
     d.cell = at<int32_t>(c->ws, p.o_cell);
     d.scan_part = at<int32_t>(c->ws, p.o_part);
-    d.rank = at<int32_t>(c->ws, p.o_rank);
+    d.kmap = at<int32_t>(c->ws, p.o_kmap);
     d.sorted = at<float4>(c->ws, p.o_sorted);
     d.perm = at<int2>(c->ws, p.o_perm);
     d.parent = at<int32_t>(c->ws, p.o_parent);

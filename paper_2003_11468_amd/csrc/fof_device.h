@@ -180,6 +180,29 @@ __device__ __forceinline__ void wave_add_by_key(unsigned long long *arr, int key
     }
 }
 
+// Runs of equal keys in consecutive lanes: on return the first lane of each
+// run holds the minimum of the run's `m` and the sum of its `c`, and the
+// function returns true there (for key >= 0 only). Six shuffle steps whatever
+// the number of distinct keys; every lane must call it.
+__device__ __forceinline__ bool wave_runs_min_add(int key, int &m, int &c)
+{
+    const int lane = lane_id();
+    const int prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || prev != key;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+    const int end = above ? __ffsll((long long)above) - 2 : 63;   // last lane of this run
+    for (int d = 1; d < 64; d <<= 1) {
+        const int om = __shfl_down(m, d, 64);
+        const int oc = __shfl_down(c, d, 64);
+        if (lane + d <= end) {
+            m = min(m, om);
+            c += oc;
+        }
+    }
+    return head && key >= 0;
+}
+
 // Atomic min of `v` into arr[key].y, one atomic per distinct key in the wave.
 __device__ __forceinline__ void wave_min_by_key(int2 *arr, int key, int v)
 {

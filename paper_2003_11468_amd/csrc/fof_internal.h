@@ -69,15 +69,15 @@ struct Plan {
     int32_t *seg_end;       // [n_segments] counts, exclusive prefix, then (after the segment pass) end slots
     int32_t *scan_part;     // [scan_tiles] tile sums of every scan level
     int32_t *bucket_hist;   // [n_buckets * n_tiles] counts, then output offsets (bucket-major)
-    float4 *staging;        // [n] bucket order: x, y, z, original index (bits); after the link: {label, size}
+    float4 *staging;        // [n] bucket order: x, y, z, original index (bits); after resolve: {label, size}
     int32_t *stpos;         // [n] staging slot of input particle i
     float4 *staging2;       // [n] segment order (cells of a segment together, unordered inside)
     int32_t *stage2_k;      // [n] staging slot of each segment-order slot
     uint32_t *occ;          // [n_segments << (seg_shift - 5) + 2] bit c: cell c holds a particle
     int32_t *wave_roots;    // [n_waves] roots among the 64 sorted slots of each wave (resolve)
     int64_t n_waves;
-    int32_t *rank;          // [n] sorted slot of each staging slot
-    float4 *sorted;         // [n] cell-sorted x, y, z; after the link: {label, size} per sorted slot
+    int32_t *kmap;          // [n] staging slot of each sorted slot
+    float4 *sorted;         // [n] cell-sorted x, y, z
     int2 *perm;             // [n] .x original index of sorted particle s, .y group minimum (at roots)
     int32_t *parent;        // [n] union-find forest over sorted indices
     int32_t *gsize;         // [n] group member count at roots (sorted indices)
@@ -109,7 +109,7 @@ int64_t max_dense_items(int64_t n, int dense_min);
 // Kernels in launch order; the ids index per-kernel timings.
 enum KernelId {
     K_CLEAR, K_BUCKET_HIST, K_BUCKET_SCAN, K_BUCKET_SCATTER, K_SEG_HIST, K_SEG_SCAN, K_SEG_SCATTER, K_CELL_SORT,
-    K_LINK_SPARSE, K_UNION_EDGES, K_LINK_DENSE, K_FLATTEN, K_RESOLVE, K_UNSORT, K_GATHER, K_COUNT_KERNELS
+    K_LINK_SPARSE, K_UNION_EDGES, K_LINK_DENSE, K_FLATTEN, K_RESOLVE, K_GATHER, K_COUNT_KERNELS
 };
 const char *kernel_name(int k);
 

@@ -27,8 +27,8 @@
 //   link           (fof_link.hip) cell-pair link search + lock-free union-find
 //   flatten  pointer jumping to the root; group minimum original index
 //            (atomic min) and member count (atomic add) at the root
-//   resolve  label and size per sorted slot, per-box group counts
-//   unsort   back into staging order (reads stay in the bucket's window)
+//   resolve  label and size per sorted slot, stored at its staging slot
+//            (writes stay in bucket windows); per-box group counts
 //   gather   back into input order (reads are runs of each tile's buckets)
 //
 // The whole translation unit is compiled with -ffp-contract=off: the double
@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
                 p.perm[dst] = make_int2(i, i);
                 p.parent[dst] = dst;
                 p.gsize[dst] = 1;
-                p.rank[p.stage2_k[k]] = dst;
+                p.kmap[dst] = p.stage2_k[k];
             }
         }
     }
@@ -509,17 +509,17 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
                 p.perm[dst] = make_int2(i, i);
                 p.parent[dst] = dst;
                 p.gsize[dst] = 1;
-                p.rank[k_of[q]] = dst;
+                p.kmap[dst] = k_of[q];
             }
     }
 }
 
-// Consecutive sorted particles mostly share their root, so the root updates
-// are combined per wave before the atomics.
+// Consecutive sorted particles often share their root, so the root updates of
+// runs of equal roots in a wave are combined before the atomics.
 __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
 {
     const int64_t s64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int root_key = -1, orig = 0;
+    int root_key = -1, m = INT_MAX, c = 0;
     if (s64 < p.n) {
         const int s = (int)s64;
         int r = s, q = p.parent[s];
@@ -530,22 +530,28 @@ __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
         if (r != s) {
             p.parent[s] = r;
             root_key = r;
-            orig = p.perm[s].x;
+            m = p.perm[s].x;
+            c = 1;
         }
     }
-    wave_min_by_key(p.perm, root_key, orig);
-    wave_add_by_key(p.gsize, root_key, 1);
+    if (wave_runs_min_add(root_key, m, c)) {
+        atomicMin(&p.perm[root_key].y, m);
+        atomicAdd(&p.gsize[root_key], c);
+    }
 }
 
-// Resolve, in sorted order: out[s] = {group label (box-local), size at the
-// root's smallest member, else 0}. Reads are local (the root of s sits near
-// s in cell order) and the write is coalesced. Roots are counted per wave:
-// a wave inside one box stores its count in wave_roots[], one that straddles
-// boxes adds per lane; k_group_count sums wave_roots per box.
+// Resolve, in sorted order: {group label (box-local), size at the member whose
+// index is the label, else 0}, stored at the particle's staging slot (kmap).
+// Reads are local (the root of s sits near s in cell order); the staging
+// slots of a stretch of sorted slots lie in a few bucket windows, and tiles go
+// to XCDs in contiguous ranges, so the scattered writes combine in each XCD's
+// L2. Roots are counted per wave: a wave inside one box stores its count in
+// wave_roots[], one that straddles boxes adds per lane; k_group_count sums
+// wave_roots per box.
 __global__ void __launch_bounds__(kBlock) k_resolve(Plan p)
 {
-    const int64_t s64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int2 *out = reinterpret_cast<int2 *>(p.sorted);   // positions are no longer needed
+    const int64_t s64 = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    int2 *staged = reinterpret_cast<int2 *>(p.staging);   // staged positions are no longer needed
     bool root = false;
     int b = 0;
     if (s64 < p.n) {
@@ -556,7 +562,7 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Plan p)
         const int2 pr = p.perm[r];
         const int m = pr.y;
         const int p0 = p.n_boxes == 1 ? 0 : (int)p.box_p0[b];
-        out[s] = make_int2(m - p0, (o == m) ? p.gsize[r] : 0);
+        staged[p.kmap[s]] = make_int2(m - p0, (o == m) ? p.gsize[r] : 0);
         root = r == s;
     }
     const int64_t wave = s64 >> 6;
@@ -612,17 +618,6 @@ __global__ void __launch_bounds__(kBlock) k_group_count(Plan p)
     }
 }
 
-// Back into staging order: the sorted slots of a bucket's staging slots lie in
-// that bucket's window, so the reads stay local.
-__global__ void __launch_bounds__(kBlock) k_unsort(Plan p)
-{
-    const int64_t k = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (k >= p.n) return;
-    const int2 *out = reinterpret_cast<const int2 *>(p.sorted);
-    int2 *staged = reinterpret_cast<int2 *>(p.staging);   // staging positions are no longer needed
-    staged[k] = out[p.rank[k]];
-}
-
 // Back into input order: a tile's particles were written as one run per
 // bucket, so these reads are runs too; the writes are coalesced.
 __global__ void __launch_bounds__(kBlock) k_gather(Plan p)
@@ -667,7 +662,7 @@ const char *kernel_name(int k)
     static const char *names[K_COUNT_KERNELS] = {
         "k_clear", "k_bucket_hist", "k_bucket_scan", "k_bucket_scatter", "k_seg_hist", "k_seg_scan", "k_seg_scatter",
         "k_cell_sort",
-        "k_link_sparse", "k_union_edges", "k_link_dense", "k_flatten", "k_resolve", "k_unsort", "k_gather"};
+        "k_link_sparse", "k_union_edges", "k_link_dense", "k_flatten", "k_resolve", "k_gather"};
     return (k >= 0 && k < K_COUNT_KERNELS) ? names[k] : "?";
 }
 
@@ -717,11 +712,10 @@ hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t)
     if (p.n == 0) return hipSuccess;
     FOF_TIMED(K_FLATTEN, hipLaunchKernelGGL(k_flatten, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
     FOF_TIMED(K_RESOLVE, {
-        hipLaunchKernelGGL(k_resolve, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p);
+        hipLaunchKernelGGL(k_resolve, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p);
         hipLaunchKernelGGL(k_group_count, dim3((unsigned)((p.n_waves + kGroupRun - 1) / kGroupRun)), dim3(kBlock), 0,
                            stream, p);
     });
-    FOF_TIMED(K_UNSORT, hipLaunchKernelGGL(k_unsort, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p));
     FOF_TIMED(K_GATHER, hipLaunchKernelGGL(k_gather, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
     return hipGetLastError();
 }

@@ -18,7 +18,7 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     lib = fof.load_library()
     names = declared_functions()
-    assert len(names) >= 15
+    assert len(names) >= 14
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(names) == sorted(fof.EXPORTS)
@@ -154,7 +154,7 @@ def test_kernel_times_need_the_option():
         assert e.value.status == fof.FOF_ERR_BAD_STATE
     finally:
         fof.fof_destroy(ctx)
-    names = [fof.fof_kernel_name(k) for k in range(15)]
+    names = [fof.fof_kernel_name(k) for k in range(14)]
     assert names[0] == "k_clear" and "k_link_dense" in names and "?" not in names
     assert fof.fof_kernel_name(99) == "?"
 
