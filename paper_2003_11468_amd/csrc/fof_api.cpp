@@ -242,14 +242,16 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.bucket_shift = 0;
     while ((last >> p.bucket_shift) >= 256) ++p.bucket_shift;
     // By default a segment holds about kSegTarget particles on average (its
-    // particles are then placed through LDS), within 2^6 .. 2^14 cells.
+    // particles are then placed through LDS), within 2^6 .. 2^13 cells (the
+    // 2^14-cell instance holds two work-groups per compute unit, the 2^13 one
+    // three, which measured faster).
     if (c->opt.sort_segment_log2) {
         p.seg_shift = c->opt.sort_segment_log2;
     } else {
         const double want = (double)fof::kSegTarget * (double)(cells > 0 ? cells : 1) /
                             (double)(offsets[n_boxes] > 0 ? offsets[n_boxes] : 1);
         p.seg_shift = fof::kSegLog2Min;
-        while (p.seg_shift < fof::kSegLog2Max && (double)(int64_t(1) << (p.seg_shift + 1)) <= want) ++p.seg_shift;
+        while (p.seg_shift < fof::kSegLog2Auto && (double)(int64_t(1) << (p.seg_shift + 1)) <= want) ++p.seg_shift;
     }
     if (p.seg_shift < p.bucket_shift - fof::kMaxSubLog2) p.seg_shift = p.bucket_shift - fof::kMaxSubLog2;
     if (p.bucket_shift < p.seg_shift) p.bucket_shift = p.seg_shift;

@@ -377,9 +377,12 @@ __device__ __forceinline__ int pad_idx(int c) { return c + (c >> 5); }
 //     written in slot order (coalesced), otherwise written directly.
 // A slot outside [0, P) cannot happen with consistent counts; it is latched
 // as error bit 1 instead of being written.
+// kLog2: the largest segment (2^kLog2 cells) the LDS of this instance holds;
+// smaller LDS lets more work-groups share a compute unit.
+template <int kLog2>
 __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
 {
-    __shared__ int cnt[(1 << kSegLog2Max) + (1 << (kSegLog2Max - 5)) + 1];
+    __shared__ int cnt[(1 << kLog2) + (1 << (kLog2 - 5)) + 1];
     __shared__ unsigned short order[kOrderCap];
     __shared__ int lds[kSegWaves];
     const int j = (int)blockIdx.x;
@@ -518,25 +521,27 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
 // runs of equal roots in a wave are combined before the atomics.
 __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
 {
-    const int64_t s64 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int root_key = -1, m = INT_MAX, c = 0;
-    if (s64 < p.n) {
-        const int s = (int)s64;
-        int r = s, q = p.parent[s];
-        while (q != r) {
-            r = q;
-            q = p.parent[r];
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < p.n; base += (int64_t)gridDim.x * kBlock) {
+        const int64_t s64 = base + threadIdx.x;
+        int root_key = -1, m = INT_MAX, c = 0;
+        if (s64 < p.n) {
+            const int s = (int)s64;
+            int r = s, q = p.parent[s];
+            while (q != r) {
+                r = q;
+                q = p.parent[r];
+            }
+            if (r != s) {
+                p.parent[s] = r;
+                root_key = r;
+                m = p.perm[s].x;
+                c = 1;
+            }
         }
-        if (r != s) {
-            p.parent[s] = r;
-            root_key = r;
-            m = p.perm[s].x;
-            c = 1;
+        if (wave_runs_min_add(root_key, m, c)) {
+            atomicMin(&p.perm[root_key].y, m);
+            atomicAdd(&p.gsize[root_key], c);
         }
-    }
-    if (wave_runs_min_add(root_key, m, c)) {
-        atomicMin(&p.perm[root_key].y, m);
-        atomicAdd(&p.gsize[root_key], c);
     }
 }
 
@@ -548,9 +553,8 @@ __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
 // L2. Roots are counted per wave: a wave inside one box stores its count in
 // wave_roots[], one that straddles boxes adds per lane; k_group_count sums
 // wave_roots per box.
-__global__ void __launch_bounds__(kBlock) k_resolve(Plan p)
+__device__ __forceinline__ void resolve_tile(const Plan &p, int64_t s64)
 {
-    const int64_t s64 = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     int2 *staged = reinterpret_cast<int2 *>(p.staging);   // staged positions are no longer needed
     bool root = false;
     int b = 0;
@@ -575,6 +579,11 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Plan p)
         if (lane_id() == 0 && wave < p.n_waves) p.wave_roots[wave] = 0;
         if (root) atomicAdd(p.n_groups + b, 1ull);
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_resolve(Plan p)
+{
+    resolve_tile(p, xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
 }
 
 // n_groups[box] += sum of wave_roots over the waves of the box (a wave belongs
@@ -631,6 +640,10 @@ __global__ void __launch_bounds__(kBlock) k_gather(Plan p)
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Grid of the persistent flatten: a few work-groups per compute unit, each
+// looping over tiles (measured faster than one work-group per tile).
+constexpr int64_t kStreamBlocks = 2048;
 inline int64_t grid_tiles(int64_t n) { return (n + kBlock - 1) / kBlock; }
 
 // Exclusive scan of data[0, len) in place; `scratch` holds the tile sums of
@@ -702,15 +715,20 @@ hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t)
     FOF_TIMED(K_SEG_SCAN, scan_exclusive(p.seg_end, p.n_segments, p.scan_part, stream));
     if (p.n > 0)
         FOF_TIMED(K_SEG_SCATTER, hipLaunchKernelGGL(k_seg_scatter, dim3(seg_tiles), dim3(kBlock), 0, stream, p));
-    FOF_TIMED(K_CELL_SORT,
-              hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)p.n_segments), dim3(kSegBlock), 0, stream, p));
+    const dim3 grid((unsigned)p.n_segments), block(kSegBlock);
+    FOF_TIMED(K_CELL_SORT, {
+        if (p.seg_shift <= 12) hipLaunchKernelGGL(k_cell_sort<12>, grid, block, 0, stream, p);
+        else if (p.seg_shift == 13) hipLaunchKernelGGL(k_cell_sort<13>, grid, block, 0, stream, p);
+        else hipLaunchKernelGGL(k_cell_sort<kSegLog2Max>, grid, block, 0, stream, p);
+    });
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
     if (p.n == 0) return hipSuccess;
-    FOF_TIMED(K_FLATTEN, hipLaunchKernelGGL(k_flatten, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
+    const unsigned flatten_grid = (unsigned)min(kStreamBlocks, grid_tiles(p.n));
+    FOF_TIMED(K_FLATTEN, hipLaunchKernelGGL(k_flatten, dim3(flatten_grid), dim3(kBlock), 0, stream, p));
     FOF_TIMED(K_RESOLVE, {
         hipLaunchKernelGGL(k_resolve, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p);
         hipLaunchKernelGGL(k_group_count, dim3((unsigned)((p.n_waves + kGroupRun - 1) / kGroupRun)), dim3(kBlock), 0,

@@ -182,6 +182,108 @@ struct SparseLds {
     int2 ebuf[kEdgeBuf];        // edge sink buffer
 };
 
+// Box parameters of the pair test, in registers.
+struct BoxPair {
+    double L, half, l2;
+    float L32, lo32, hi32;
+    __device__ __forceinline__ static BoxPair of(const BoxDev &bd)
+    {
+        return BoxPair{bd.L, bd.half, bd.l2, bd.L32, bd.lo32, bd.hi32};
+    }
+};
+
+// The pair loop of the per-particle search over the wave's flattened units.
+// Merge-path split: lane l takes the pairs [T l / 64, T (l + 1) / 64) of the
+// wave's T pairs, finds the unit of its first pair by one binary search, then
+// walks forward; every lane runs the same number of steps. kOneBox: every
+// home particle of the tile lies in one box, whose parameters are `bp`.
+template <bool kFP64, bool kStats, bool kOneBox>
+__device__ __forceinline__ void sparse_pairs(const Plan &p, SparseLds &L, EdgeSink &sink, int s0, int n_units,
+                                             int n_pairs, int b, BoxPair bp, unsigned long long &tests,
+                                             unsigned long long &links, unsigned long long &band, unsigned &retries)
+{
+    const int lane = lane_id();
+    const bool strict = p.strict != 0;
+    const int q0 = (int)(((int64_t)n_pairs * lane) >> 6);
+    const int q1 = (int)(((int64_t)n_pairs * (lane + 1)) >> 6);
+    int u = 0;
+#pragma unroll
+    for (int step = 512; step > 0; step >>= 1) {
+        const int nxt = u + step;
+        if (nxt < n_units && L.start[nxt] <= q0) u = nxt;
+    }
+    int next_start = L.start[u + 1];
+    int jq = L.j0[u] + (q0 - L.start[u]);   // candidate of pair q
+    int tag = L.tag[u];
+    float4 h = L.home[tag >> 8];
+    // four steps at a time: their candidate loads are in flight together
+    constexpr int kAhead = 4;
+    const int steps = (n_pairs + 63) >> 6;
+    int q = q0;
+    for (int k = 0; k < steps; k += kAhead) {
+        int jj[kAhead], tg[kAhead];
+        float4 hh[kAhead], cc[kAhead];
+        bool lv[kAhead];
+#pragma unroll
+        for (int a = 0; a < kAhead; ++a) {
+            lv[a] = q < q1 && k + a < steps;
+            if (lv[a] && q == next_start) {   // the next unit starts here
+                ++u;
+                next_start = L.start[u + 1];
+                jq = L.j0[u];
+                tag = L.tag[u];
+                h = L.home[tag >> 8];
+            }
+            jj[a] = jq;
+            tg[a] = tag;
+            hh[a] = h;
+            if (lv[a]) {
+                ++jq;
+                ++q;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < kAhead; ++a)
+            if (lv[a]) cc[a] = p.sorted[jj[a]];
+#pragma unroll
+        for (int a = 0; a < kAhead; ++a) {
+            const int hl = tg[a] >> 8, code = tg[a] & 63;
+            BoxPair bx = bp;
+            if constexpr (!kOneBox) {
+                const int bq = __shfl(b, hl, 64);   // all lanes take part in the shuffle
+                if (lv[a]) bx = BoxPair::of(p.boxes[bq]);
+            }
+            bool link = false;
+            if (lv[a]) {
+                const float4 c = cc[a];
+                const float4 hp = hh[a];
+                if constexpr (kFP64) {
+                    const double tx = ((double)hp.x - (double)c.x) + axis_shift(code & 3, bx.L);
+                    const double ty = ((double)hp.y - (double)c.y) + axis_shift((code >> 2) & 3, bx.L);
+                    const double tz = ((double)hp.z - (double)c.z) + axis_shift((code >> 4) & 3, bx.L);
+                    const double sxy = tx * tx + ty * ty;
+                    const double r2 = sxy + tz * tz;
+                    link = strict ? (r2 < bx.l2) : (r2 <= bx.l2);
+                } else {
+                    const float dx = axis_diff(hp.x, c.x, code & 3, bx.L32);
+                    const float dy = axis_diff(hp.y, c.y, (code >> 2) & 3, bx.L32);
+                    const float dz = axis_diff(hp.z, c.z, (code >> 4) & 3, bx.L32);
+                    const float rr = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    if (rr < bx.lo32) link = true;
+                    else if (rr > bx.hi32) link = false;
+                    else {
+                        if (kStats) ++band;
+                        link = link_fp64(hp.x, hp.y, hp.z, c.x, c.y, c.z, bx.L, bx.half, bx.l2, strict);
+                    }
+                }
+                if (kStats) ++tests;
+                if (kStats && link) ++links;
+            }
+            sink.push(p, link, s0 + hl, jj[a], retries);
+        }
+    }
+}
+
 template <bool kFP64, bool kStats>
 __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
 {
@@ -302,90 +404,15 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
             L.home[lane] = pi;
         }
         __builtin_amdgcn_wave_barrier();
-        // a tile inside one box uses that box's parameters for every pair;
-        // otherwise each pair reads the box of its home particle
+        // a tile inside one box keeps that box's parameters in registers for
+        // every pair; otherwise each pair reads the box of its home particle
         const int b0 = __builtin_amdgcn_readfirstlane(b);
-        const bool one_box = __ballot(b != b0) == 0;
-        const bool strict = p.strict != 0;
-        // Merge-path split: lane l takes the pairs [T l / 64, T (l + 1) / 64) of
-        // the wave's T pairs, finds the unit of its first pair by one binary
-        // search, then walks forward; every lane runs the same number of steps.
-        const int q0 = (int)(((int64_t)n_pairs * lane) >> 6);
-        const int q1 = (int)(((int64_t)n_pairs * (lane + 1)) >> 6);
-        int u = 0;
-#pragma unroll
-        for (int step = 512; step > 0; step >>= 1) {
-            const int nxt = u + step;
-            if (nxt < n_units && L.start[nxt] <= q0) u = nxt;
-        }
-        int next_start = L.start[u + 1];
-        int jq = L.j0[u] + (q0 - L.start[u]);   // candidate of pair q
-        int tag = L.tag[u];
-        float4 h = L.home[tag >> 8];
-        // four steps at a time: their candidate loads are in flight together
-        constexpr int kAhead = 4;
-        const int steps = (n_pairs + 63) >> 6;
-        int q = q0;
-        for (int k = 0; k < steps; k += kAhead) {
-            int jj[kAhead], tg[kAhead];
-            float4 hh[kAhead], cc[kAhead];
-            bool lv[kAhead];
-#pragma unroll
-            for (int a = 0; a < kAhead; ++a) {
-                lv[a] = q < q1 && k + a < steps;
-                if (lv[a] && q == next_start) {   // the next unit starts here
-                    ++u;
-                    next_start = L.start[u + 1];
-                    jq = L.j0[u];
-                    tag = L.tag[u];
-                    h = L.home[tag >> 8];
-                }
-                jj[a] = jq;
-                tg[a] = tag;
-                hh[a] = h;
-                if (lv[a]) {
-                    ++jq;
-                    ++q;
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < kAhead; ++a)
-                if (lv[a]) cc[a] = p.sorted[jj[a]];
-#pragma unroll
-            for (int a = 0; a < kAhead; ++a) {
-                const int hl = tg[a] >> 8, code = tg[a] & 63;
-                const int s = (int)(tile * 64) + hl;
-                const int bq = one_box ? b0 : __shfl(b, hl, 64);   // all lanes take part in the shuffle
-                bool link = false;
-                if (lv[a]) {
-                    const float4 c = cc[a];
-                    const float4 hp = hh[a];
-                    const BoxDev &bd = box_of(p, bq);
-                    if constexpr (kFP64) {
-                        const double tx = ((double)hp.x - (double)c.x) + axis_shift(code & 3, bd.L);
-                        const double ty = ((double)hp.y - (double)c.y) + axis_shift((code >> 2) & 3, bd.L);
-                        const double tz = ((double)hp.z - (double)c.z) + axis_shift((code >> 4) & 3, bd.L);
-                        const double sxy = tx * tx + ty * ty;
-                        const double r2 = sxy + tz * tz;
-                        link = strict ? (r2 < bd.l2) : (r2 <= bd.l2);
-                    } else {
-                        const float dx = axis_diff(hp.x, c.x, code & 3, bd.L32);
-                        const float dy = axis_diff(hp.y, c.y, (code >> 2) & 3, bd.L32);
-                        const float dz = axis_diff(hp.z, c.z, (code >> 4) & 3, bd.L32);
-                        const float rr = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        if (rr < bd.lo32) link = true;
-                        else if (rr > bd.hi32) link = false;
-                        else {
-                            if (kStats) ++band;
-                            link = link_fp64(hp.x, hp.y, hp.z, c.x, c.y, c.z, bd.L, bd.half, bd.l2, strict);
-                        }
-                    }
-                    if (kStats) ++tests;
-                    if (kStats && link) ++links;
-                }
-                sink.push(p, link, s, jj[a], retries);
-            }
-        }
+        if (__ballot(b != b0) == 0)
+            sparse_pairs<kFP64, kStats, true>(p, L, sink, (int)(tile * 64), n_units, n_pairs, b, BoxPair::of(box_of(p, b0)),
+                                              tests, links, band, retries);
+        else
+            sparse_pairs<kFP64, kStats, false>(p, L, sink, (int)(tile * 64), n_units, n_pairs, b, BoxPair{},
+                                               tests, links, band, retries);
         __builtin_amdgcn_wave_barrier();
     }
     sink.flush(p, retries);
