@@ -114,7 +114,10 @@ __global__ void __launch_bounds__(kBlock) k_bucket_scatter(Plan p)
     __shared__ unsigned char stage_b[kSortTile];
     __shared__ int cnt[kMaxBuckets], first[kMaxBuckets], dst0[kMaxBuckets];
     __shared__ int lds[kBlock / 64];
-    const int64_t tile = blockIdx.x;
+    // tiles go to XCDs in contiguous ranges: neighbouring tiles' runs share
+    // cache lines of the staging buffer
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= p.n_tiles) return;
     const int64_t base = tile * kSortTile;
     for (int b = threadIdx.x; b < kMaxBuckets; b += kBlock) cnt[b] = 0;
     __syncthreads();
@@ -251,7 +254,7 @@ __device__ __forceinline__ int seg_tile(const Plan &p, int *info, int *lds, int 
     if (t == 0) info[0] = -1;
     int total;
     const int first = block_excl_scan<kBlock>(tiles, lds, &total);   // synchronises after info[0] = -1
-    const int g = (int)blockIdx.x;
+    const int g = (int)xcd_tile(blockIdx.x, gridDim.x);   // contiguous tile ranges per XCD
     if (g >= first && g < first + tiles) {
         info[0] = t;
         info[1] = start + (g - first) * kSortTile;
@@ -631,7 +634,7 @@ __global__ void __launch_bounds__(kBlock) k_group_count(Plan p)
 // bucket, so these reads are runs too; the writes are coalesced.
 __global__ void __launch_bounds__(kBlock) k_gather(Plan p)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= p.n) return;
     const int2 *staged = reinterpret_cast<const int2 *>(p.staging);
     const int2 v = staged[p.stpos[i]];
@@ -703,13 +706,13 @@ hipError_t launch_clear(const Plan &p, hipStream_t stream, KernelTimer *t)
 
 hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
-    const unsigned seg_tiles = (unsigned)(p.n_tiles + p.n_buckets);
+    const unsigned seg_tiles = xcd_grid(p.n_tiles + p.n_buckets);
     if (p.n > 0) {
         const unsigned tiles = (unsigned)p.n_tiles;
         FOF_TIMED(K_BUCKET_HIST, hipLaunchKernelGGL(k_bucket_hist, dim3(tiles), dim3(kBlock), 0, stream, p));
         FOF_TIMED(K_BUCKET_SCAN, scan_exclusive(p.bucket_hist, (int64_t)p.n_buckets * p.n_tiles, p.scan_part, stream));
         FOF_TIMED(K_BUCKET_SCATTER,
-                  hipLaunchKernelGGL(k_bucket_scatter, dim3(tiles), dim3(kBlock), 0, stream, p));
+                  hipLaunchKernelGGL(k_bucket_scatter, dim3(xcd_grid(tiles)), dim3(kBlock), 0, stream, p));
         FOF_TIMED(K_SEG_HIST, hipLaunchKernelGGL(k_seg_hist, dim3(seg_tiles), dim3(kBlock), 0, stream, p));
     }
     FOF_TIMED(K_SEG_SCAN, scan_exclusive(p.seg_end, p.n_segments, p.scan_part, stream));
@@ -734,7 +737,7 @@ hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t)
         hipLaunchKernelGGL(k_group_count, dim3((unsigned)((p.n_waves + kGroupRun - 1) / kGroupRun)), dim3(kBlock), 0,
                            stream, p);
     });
-    FOF_TIMED(K_GATHER, hipLaunchKernelGGL(k_gather, dim3(grid_for(p.n)), dim3(kBlock), 0, stream, p));
+    FOF_TIMED(K_GATHER, hipLaunchKernelGGL(k_gather, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p));
     return hipGetLastError();
 }
 
