@@ -23,6 +23,19 @@ __device__ __forceinline__ int find_box(const int64_t *p0, int n_boxes, int64_t 
     return lo;
 }
 
+// find_box for one index per lane: the box of the first active lane is found
+// once (uniform, scalar loads); only lanes outside it search on their own.
+// Consecutive particles, in input or cell order, nearly always share a box.
+__device__ __forceinline__ int find_box_wave(const int64_t *p0, int n_boxes, int64_t i)
+{
+    const unsigned lo32 = __builtin_amdgcn_readfirstlane((unsigned)(uint64_t)i);
+    const unsigned hi32 = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)i >> 32));
+    const int64_t i0 = (int64_t)(((uint64_t)hi32 << 32) | lo32);
+    const int b0 = find_box(p0, n_boxes, i0);
+    if (i >= p0[b0] && i < p0[b0 + 1]) return b0;
+    return find_box(p0, n_boxes, i);
+}
+
 // Cell coordinate along one axis: floor(x * nc / L) clamped to [0, nc - 1].
 // The product is formed in double, so for L = 1 it is exact; a NaN lands in
 // cell 0 (the coordinate error is latched separately).

@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(kBlock) k_clear(Plan p)
 // and inside [0, L).
 __device__ __forceinline__ int input_key(const Plan &p, int64_t i, float &x, float &y, float &z, bool &ok)
 {
-    const int b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, i);
+    const int b = p.n_boxes == 1 ? 0 : find_box_wave(p.box_p0, p.n_boxes, i);
     const BoxDev &bd = box_of(p, b);
     x = p.pos[3 * i + 0];
     y = p.pos[3 * i + 1];
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(ScanArgs a)
 // Cell of a staged particle (x, y, z, original index as bits).
 __device__ __forceinline__ int staged_cell(const Plan &p, const float4 &v)
 {
-    const int b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, __float_as_int(v.w));
+    const int b = p.n_boxes == 1 ? 0 : find_box_wave(p.box_p0, p.n_boxes, __float_as_int(v.w));
     return particle_cell(box_of(p, b), v.x, v.y, v.z);
 }
 
@@ -563,7 +563,7 @@ __device__ __forceinline__ void resolve_tile(const Plan &p, int64_t s64)
     int b = 0;
     if (s64 < p.n) {
         const int s = (int)s64;
-        b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, s64);
+        b = p.n_boxes == 1 ? 0 : find_box_wave(p.box_p0, p.n_boxes, s64);
         const int r = p.parent[s];
         const int o = p.perm[s].x;
         const int2 pr = p.perm[r];

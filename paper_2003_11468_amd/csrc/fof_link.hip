@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
         int b = 0;
         if (s64 < p.n) {
             const int s = (int)s64;
-            b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, s64);
+            b = p.n_boxes == 1 ? 0 : find_box_wave(p.box_p0, p.n_boxes, s64);
             const BoxDev &bd = box_of(p, b);
             pi = p.sorted[s];
             const int nc = bd.nc;
