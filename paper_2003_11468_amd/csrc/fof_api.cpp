@@ -195,6 +195,7 @@ void fp32_thresholds(BoxDev &b, double lx)
 }
 
 constexpr int kDefaultDenseMin = 32;
+constexpr int kMaxSubK = 10;             // at most 1000 sub-cells per dense cell
 constexpr int kDenseBlocks = 2048;
 constexpr int kSparseBlocks = 1024;
 
@@ -229,6 +230,15 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
         b.inv_h = (double)nc / L;
         b.l2 = l * l;
         fp32_thresholds(b, l);
+        // Sub-cells of side L / (nc k) with a diagonal at most l_x (1 - 1e-6): any
+        // two particles in one are linked under both predicates (the margin
+        // dwarfs every rounding error), so dense cells can be pre-merged by
+        // sub-cell before the pair search. Used only for k <= kMaxSubK.
+        {
+            const double side = L / (double)nc;
+            const double k = std::ceil(side * std::sqrt(3.0) / (l * (1.0 - 1e-6)));
+            b.sub_k = (k >= 1.0 && k <= (double)kMaxSubK) ? (int32_t)k : 0;
+        }
         if (c->opt.predicate == FOF_PRED_FP32_FILTER && b.use_fp64) ++p.fp64_boxes;
         cells += nc * nc * nc;
         if (cells > kMaxCells) return FOF_ERR_UNSUPPORTED;

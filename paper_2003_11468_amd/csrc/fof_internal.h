@@ -23,7 +23,7 @@ struct BoxDev {
     float L32;            // L as FP32 (equal to L whenever the FP32 filter is used)
     float lo32;           // FP32 r2 below this: linked (proven)
     float hi32;           // FP32 r2 above this: not linked (proven)
-    float pad;
+    int32_t sub_k;        // sub-cells per cell axis whose diagonal is below l_x (0: none used)
 };
 
 // Device counters (one block of the workspace, cleared by every build).
