@@ -110,7 +110,9 @@ typedef struct {
     float hi32;              /* FP32 squared distance above this: not linked, proven */
     int32_t fp64_only;       /* 1: the FP32 filter cannot be proven for this box; every pair is
                                 decided in double */
-    int32_t reserved[3];
+    int32_t sub_cells_per_axis; /* k: dense cells are pre-merged by k^3 sub-cells whose diagonal is
+                                at most l_x (1 - 1e-6); 0 = no pre-merge */
+    int32_t reserved[2];
 } fof_box_info;
 
 /* Host only: the cell count per axis and FP32 thresholds for a box of

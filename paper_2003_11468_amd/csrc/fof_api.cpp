@@ -199,6 +199,18 @@ constexpr int kMaxSubK = 10;             // at most 1000 sub-cells per dense cel
 constexpr int kDenseBlocks = 2048;
 constexpr int kSparseBlocks = 1024;
 
+// Sub-cells per cell axis for the pre-merge of dense cells: k sub-cells of
+// side L / (nc k) whose diagonal is at most l_x (1 - 1e-6), so that any two
+// particles in one are linked under both predicates (the margin dwarfs every
+// rounding error of the double predicate and of the sub-cell assignment).
+// 0 (no pre-merge) when more than kMaxSubK would be needed.
+int32_t sub_cells_per_axis(double L, int64_t nc, double lx)
+{
+    const double side = L / (double)nc;
+    const double k = std::ceil(side * std::sqrt(3.0) / (lx * (1.0 - 1e-6)));
+    return (k >= 1.0 && k <= (double)kMaxSubK) ? (int32_t)k : 0;
+}
+
 int dense_min_of(const fof_options &o) { return o.dense_min > 0 ? o.dense_min : kDefaultDenseMin; }
 
 fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box, const double *lx, int32_t n_boxes,
@@ -230,15 +242,7 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
         b.inv_h = (double)nc / L;
         b.l2 = l * l;
         fp32_thresholds(b, l);
-        // Sub-cells of side L / (nc k) with a diagonal at most l_x (1 - 1e-6): any
-        // two particles in one are linked under both predicates (the margin
-        // dwarfs every rounding error), so dense cells can be pre-merged by
-        // sub-cell before the pair search. Used only for k <= kMaxSubK.
-        {
-            const double side = L / (double)nc;
-            const double k = std::ceil(side * std::sqrt(3.0) / (l * (1.0 - 1e-6)));
-            b.sub_k = (k >= 1.0 && k <= (double)kMaxSubK) ? (int32_t)k : 0;
-        }
+        b.sub_k = sub_cells_per_axis(L, nc, l);
         if (c->opt.predicate == FOF_PRED_FP32_FILTER && b.use_fp64) ++p.fp64_boxes;
         cells += nc * nc * nc;
         if (cells > kMaxCells) return FOF_ERR_UNSUPPORTED;
@@ -658,6 +662,7 @@ fof_status fof_describe_box(const fof_options *opt, int64_t n_particles, double 
     out->lo32 = b.lo32;
     out->hi32 = b.hi32;
     out->fp64_only = b.use_fp64;
+    out->sub_cells_per_axis = sub_cells_per_axis(box, nc, lx);
     return FOF_OK;
 }
 

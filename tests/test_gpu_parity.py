@@ -196,6 +196,21 @@ def test_cell_sort_segments(segment_log2):
     assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and np.array_equal(ng, ref[2])
 
 
+# Tight clumps fill sub-cells of dense cells with many particles, so the
+# sub-cell pre-merge does most of the merging before the pair search.
+def test_dense_cells_premerged_by_sub_cells():
+    rng = np.random.default_rng(41)
+    centres = rng.random((300, 3))
+    pts = (centres[:, None, :] + rng.normal(0.0, 0.002, (300, 60, 3))) % 1.0
+    pos = pts.reshape(-1, 3).astype(np.float32)
+    pos[pos >= np.float32(1.0)] = 0
+    for cf in (1.0, 2.0, 4.0):
+        assert fof.fof_describe_box(len(pos), 1.0, 0.004, fof.make_options(cell_factor=cf))["sub_cells_per_axis"] > 0
+        for strict in (False, True):
+            for predicate in PREDICATES:
+                assert_single(pos, 0.004, strict=strict, predicate=predicate, cell_factor=cf, dense_min=8)
+
+
 def test_uniform32k_and_strict():
     w = synth.make("uniform32k")
     for predicate in PREDICATES:

@@ -117,3 +117,37 @@ def test_without_the_band_fp32_alone_would_be_wrong():
         wrong += int(np.count_nonzero((plain <= l2_32) != (r64 <= l2)))
         wrong += int(np.count_nonzero((fused <= l2_32) != (r64 <= l2)))
     assert wrong > 0
+
+
+def test_premerge_sub_cells_are_inside_the_linking_length():
+    """Dense cells are pre-merged by k^3 sub-cells: every two points of one must
+    be linked, so the sub-cell diagonal must stay below l_x with room for the
+    double predicate's rounding; k must be the smallest such count."""
+    rng = np.random.default_rng(11)
+    seen = set()
+    for _ in range(400):
+        n = int(rng.integers(27, 10 ** 7))
+        L = float(rng.choice([1.0, 8.0, 0.125, 1024.0, 0.1]))
+        lx = L * float(rng.uniform(0.001, 0.3)) / max(1.0, n ** (1 / 3) / 4)
+        cf = float(rng.choice([0.0, 1.0, 1.5, 2.0, 3.0, 4.0, 7.0]))
+        try:
+            info = fof.fof_describe_box(n, L, lx, fof.make_options(cell_factor=cf))
+        except fof.FoFError:
+            continue
+        nc, k = info["cells_per_axis"], info["sub_cells_per_axis"]
+        side = L / nc
+        need = side * np.sqrt(3.0) / (lx * (1 - 1e-6))
+        if k:
+            assert 1 <= k <= 10
+            assert side / k * np.sqrt(3.0) <= lx * (1 - 1e-6) * (1 + 1e-12)
+            assert k == int(np.ceil(need))
+            # the FP64 predicate of two points at the far corners of one sub-cell links
+            a = np.zeros(3, dtype=np.float32)
+            s = side / k
+            b = np.full(3, s * (1 - 1e-7), dtype=np.float64).astype(np.float32)
+            t = b.astype(np.float64) - a.astype(np.float64)
+            assert float((t[0] * t[0] + t[1] * t[1]) + t[2] * t[2]) < info["l2"]
+        else:
+            assert need > 10
+        seen.add(k)
+    assert 0 in seen and len(seen) > 3
