@@ -256,6 +256,13 @@ def main():
     log(f"timing fp32_filter cell_factor={cfg['cell_factor']} dense_min={cfg['dense_min']}")
     ms, kern = timed_steps(torch, fof, f, pos, w, args.steps, args.warmup, label, size)
     groups = int(f.n_groups(w.n_boxes).sum())
+    # group catalogue of the last step (groups of more than 20 members, the paper's cut), not in the step
+    cat = {"min_size": 21}
+    e0, e1 = event(torch, f.stream), None
+    cat["groups"] = fof.fof_catalogue(f.ctx, label, size, 21)
+    e1 = event(torch, f.stream)
+    torch.cuda.synchronize()
+    cat["count_ms"] = round(e0.elapsed_time(e1), 4)
     lab32 = label.cpu().numpy()
     size32 = size.cpu().numpy()
     f.close()
@@ -398,6 +405,7 @@ def main():
                    "cell_factor": cfg["cell_factor"], "dense_min": cfg["dense_min"], "n_cells": st["n_cells"],
                    "parallelism": "single GPU"},
         "n_groups": groups,
+        "catalogue": cat,
         "kernels": passes,
         "stats": {k: st[k] for k in ("pair_tests", "sparse_pair_tests", "links", "band_hits", "cas_retries",
                                      "queued_links", "dense_items")},

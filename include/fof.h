@@ -115,6 +115,21 @@ typedef struct {
     int32_t reserved[2];
 } fof_box_info;
 
+/* Group catalogue (the step after labelling; the paper's group-size pass,
+ * Section 3.4.1-3.4.2, and its catalogue of groups above a size cut): the
+ * groups of at least `min_size` members of the outputs of the last
+ * fof_finalize on this context (`d_group_index`, `d_group_size`, same
+ * particles and boxes), in order of box and label. For group g:
+ * d_first[g] = its label (smallest box-local member index), d_size[g] = its
+ * member count, d_box[g] = its box (d_box may be NULL). At most `capacity`
+ * entries are written (capacity 0 counts only); *h_count receives the number
+ * of groups selected, which may exceed capacity. Device arrays are int32 and
+ * caller-owned. Enqueues on the context's stream and waits for it.
+ * Errors: FOF_ERR_INVALID_ARG (null pointer, min_size < 1, capacity < 0),
+ * FOF_ERR_BAD_STATE (no build on this context), FOF_ERR_DEVICE. */
+fof_status fof_catalogue(fof_ctx *ctx, const int32_t *d_group_index, const int32_t *d_group_size, int32_t min_size,
+                         int32_t *d_first, int32_t *d_size, int32_t *d_box, int64_t capacity, int64_t *h_count);
+
 /* Host only: the cell count per axis and FP32 thresholds for a box of
  * `n_particles` particles, side `box` and linking length `lx` under options
  * `opt` (NULL = defaults). Same validation as fof_workspace_bytes. */

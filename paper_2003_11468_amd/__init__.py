@@ -62,7 +62,7 @@ _lib = None
 EXPORTS = ["fof_default_options", "fof_create", "fof_set_stream", "fof_workspace_bytes", "fof_set_workspace",
            "fof_build_cells", "fof_link", "fof_finalize", "fof_read_n_groups", "fof_get_stats",
            "fof_graph_capture", "fof_graph_launch", "fof_destroy", "fof_status_string", "fof_get_kernel_times",
-           "fof_kernel_name", "fof_describe_box"]
+           "fof_kernel_name", "fof_describe_box", "fof_catalogue"]
 
 
 def load_library():
@@ -94,6 +94,7 @@ def load_library():
         "fof_kernel_name": (ctypes.c_char_p, [i32]),
         "fof_describe_box": (ctypes.c_int, [ctypes.POINTER(Options), i64, ctypes.c_double, ctypes.c_double,
                                             ctypes.POINTER(BoxInfo)]),
+        "fof_catalogue": (ctypes.c_int, [vp, vp, vp, i32, vp, vp, vp, i64, i64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -233,6 +234,14 @@ def fof_describe_box(n_particles: int, box: float, lx: float, opt: Options | Non
     return {k: getattr(info, k) for k, _ in info._fields_ if k != "reserved"}
 
 
+def fof_catalogue(ctx, label, size, min_size: int, first=None, gsize=None, gbox=None, capacity: int = 0) -> int:
+    """Groups of at least min_size members (see include/fof.h); returns how many there are."""
+    count = ctypes.c_int64(0)
+    _check(load_library().fof_catalogue(ctx, _dptr(label), _dptr(size), int(min_size), _dptr(first), _dptr(gsize),
+                                        _dptr(gbox), int(capacity), ctypes.byref(count)), "fof_catalogue")
+    return int(count.value)
+
+
 def fof_kernel_name(k: int) -> str:
     return load_library().fof_kernel_name(k).decode()
 
@@ -320,6 +329,17 @@ class FoF:
 
     def kernel_times(self) -> dict:
         return fof_get_kernel_times(self.ctx)
+
+    def catalogue(self, label, size, min_size: int = 1):
+        """(first, size, box) tensors of the groups of at least min_size members of the
+        last run's outputs, in order of box and label."""
+        t = self._torch
+        n = fof_catalogue(self.ctx, label, size, min_size)
+        dev = self.stream.device
+        first, gsize, gbox = (t.empty(max(n, 1), dtype=t.int32, device=dev) for _ in range(3))
+        got = fof_catalogue(self.ctx, label, size, min_size, first, gsize, gbox, n)
+        assert got == n
+        return first[:n], gsize[:n], gbox[:n]
 
     def _check_pos(self, pos, offsets):
         t = self._torch

@@ -276,7 +276,9 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     {
         const int64_t a = fof::scan_scratch_for(p.n_segments);
         const int64_t b = fof::scan_scratch_for((int64_t)p.n_buckets * p.n_tiles);
+        const int64_t t = fof::scan_scratch_for(p.n_tiles + 1);   // the group catalogue
         p.scan_tiles = a > b ? a : b;
+        if (t > p.scan_tiles) p.scan_tiles = t;
     }
     if ((int64_t)p.n_buckets * p.n_tiles > (int64_t)INT32_MAX) return FOF_ERR_UNSUPPORTED;
 
@@ -306,7 +308,7 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.max_edges = (p.max_edges + fof::kEdgeSlices - 1) / fof::kEdgeSlices * fof::kEdgeSlices;
     p.o_edges = take(sizeof(int32_t) * 2 * (size_t)p.max_edges);
     p.o_edge_fill = take(sizeof(uint32_t) * fof::kEdgeSlices);
-    p.o_hist = take(sizeof(int32_t) * (size_t)p.n_buckets * (size_t)p.n_tiles);
+    p.o_hist = take(sizeof(int32_t) * ((size_t)p.n_buckets * (size_t)p.n_tiles + 1));
     p.o_staging = take(sizeof(float) * 4 * n);
     p.o_stpos = take(sizeof(int32_t) * n);
     p.o_wave_roots = take(sizeof(int32_t) * ((n + 63) / 64));
@@ -544,6 +546,27 @@ fof_status fof_finalize(fof_ctx *ctx, int32_t *d_group_index, int32_t *d_group_s
     ctx->state = 0;   // the forest is consumed: a new build is needed
     if (st != FOF_OK) return st;
     if (h_n_groups) return read_back(ctx, h_n_groups, nullptr);
+    return FOF_OK;
+}
+
+fof_status fof_catalogue(fof_ctx *ctx, const int32_t *d_group_index, const int32_t *d_group_size, int32_t min_size,
+                         int32_t *d_first, int32_t *d_size, int32_t *d_box, int64_t capacity, int64_t *h_count)
+{
+    if (!ctx || !h_count || min_size < 1 || capacity < 0) return FOF_ERR_INVALID_ARG;
+    *h_count = 0;
+    if (!ctx->planned || !ctx->ws) return FOF_ERR_BAD_STATE;
+    if (ctx->plan.n > 0 && (!d_group_index || !d_group_size)) return FOF_ERR_INVALID_ARG;
+    if (capacity > 0 && (!d_first || !d_size)) return FOF_ERR_INVALID_ARG;
+    const fof::Plan &p = ctx->dev;
+    fof_status st = dev_err(fof::launch_catalogue(p, d_group_index, d_group_size, min_size, d_first, d_size, d_box,
+                                                  capacity, ctx->stream));
+    if (st != FOF_OK) return st;
+    int total = 0;
+    if (hipMemcpyAsync(&total, p.bucket_hist + p.n_tiles, sizeof(int), hipMemcpyDeviceToHost, ctx->stream) !=
+        hipSuccess)
+        return FOF_ERR_DEVICE;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return FOF_ERR_DEVICE;
+    *h_count = total;
     return FOF_OK;
 }
 

@@ -68,7 +68,8 @@ struct Plan {
     int32_t *cell;          // [n_cells + 1] first sorted slot of each cell; cell[n_cells] = n
     int32_t *seg_end;       // [n_segments] counts, exclusive prefix, then (after the segment pass) end slots
     int32_t *scan_part;     // [scan_tiles] tile sums of every scan level
-    int32_t *bucket_hist;   // [n_buckets * n_tiles] counts, then output offsets (bucket-major)
+    int32_t *bucket_hist;   // [n_buckets * n_tiles + 1] counts, then output offsets (bucket-major);
+                            // the group catalogue reuses it for its tile counts
     float4 *staging;        // [n] bucket order: x, y, z, original index (bits); after resolve: {label, size}
     int32_t *stpos;         // [n] staging slot of input particle i
     float4 *staging2;       // [n] segment order (cells of a segment together, unordered inside)
@@ -126,5 +127,9 @@ hipError_t launch_clear(const Plan &p, hipStream_t stream, KernelTimer *t);
 hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t);
 hipError_t launch_link(const Plan &p, hipStream_t stream, KernelTimer *t);
 hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t);
+// Groups of at least min_size members (fof_kernels.hip); the total is left in
+// p.bucket_hist[p.n_tiles].
+hipError_t launch_catalogue(const Plan &p, const int32_t *label, const int32_t *size, int min_size,
+                            int32_t *g_first, int32_t *g_size, int32_t *g_box, int64_t capacity, hipStream_t stream);
 
 }  // namespace fof

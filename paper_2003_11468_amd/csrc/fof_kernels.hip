@@ -642,6 +642,58 @@ __global__ void __launch_bounds__(kBlock) k_gather(Plan p)
     p.size[i] = v.y;
 }
 
+__global__ void k_clear_ints(int *a, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = 0;
+}
+
+// ------------------------------------------------------------- catalogue --
+// Groups of at least min_size members, in input order (box by box, label
+// ascending): a group appears once, at the particle whose index is its label,
+// the only one with a non-zero size. Per tile of kSortTile particles: count,
+// then an exclusive prefix over the tiles, then each tile writes its groups
+// in order (thread t owns kSortItems consecutive particles).
+
+__global__ void __launch_bounds__(kBlock) k_cat_count(const Plan p, const int32_t *size, int min_size, int *tile_count)
+{
+    __shared__ int lds[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) c += (base + k < p.n && size[base + k] >= min_size) ? 1 : 0;
+    int total;
+    block_excl_scan<kBlock>(c, lds, &total);
+    if (threadIdx.x == 0) tile_count[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cat_write(const Plan p, const int32_t *label, const int32_t *size,
+                                                      int min_size, const int *tile_off, int32_t *g_first,
+                                                      int32_t *g_size, int32_t *g_box, int64_t capacity)
+{
+    __shared__ int lds[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    bool take[kSortItems];
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        take[k] = base + k < p.n && size[base + k] >= min_size;
+        c += take[k] ? 1 : 0;
+    }
+    int total;
+    int64_t at = (int64_t)tile_off[blockIdx.x] + block_excl_scan<kBlock>(c, lds, &total);
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k)
+        if (take[k]) {
+            if (at < capacity) {
+                const int64_t i = base + k;
+                g_first[at] = label[i];
+                g_size[at] = size[i];
+                if (g_box) g_box[at] = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, i);
+            }
+            ++at;
+        }
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // Grid of the persistent flatten: a few work-groups per compute unit, each
@@ -724,6 +776,22 @@ hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t)
         else if (p.seg_shift == 13) hipLaunchKernelGGL(k_cell_sort<13>, grid, block, 0, stream, p);
         else hipLaunchKernelGGL(k_cell_sort<kSegLog2Max>, grid, block, 0, stream, p);
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_catalogue(const Plan &p, const int32_t *label, const int32_t *size, int min_size,
+                            int32_t *g_first, int32_t *g_size, int32_t *g_box, int64_t capacity, hipStream_t stream)
+{
+    // tile counts go to the bucket histogram (free after the build), then an
+    // exclusive prefix over n_tiles + 1 entries leaves the total in the last
+    int *count = p.bucket_hist;
+    const unsigned tiles = (unsigned)p.n_tiles;
+    hipLaunchKernelGGL(k_clear_ints, dim3(1), dim3(kBlock), 0, stream, count + p.n_tiles, 1);
+    if (tiles) hipLaunchKernelGGL(k_cat_count, dim3(tiles), dim3(kBlock), 0, stream, p, size, min_size, count);
+    scan_exclusive(count, p.n_tiles + 1, p.scan_part, stream);
+    if (tiles)
+        hipLaunchKernelGGL(k_cat_write, dim3(tiles), dim3(kBlock), 0, stream, p, label, size, min_size, count,
+                           g_first, g_size, g_box, capacity);
     return hipGetLastError();
 }
 

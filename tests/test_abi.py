@@ -146,6 +146,20 @@ def test_null_arguments():
         fof.fof_destroy(ctx)
 
 
+def test_catalogue_validation():
+    ctx = _ctx()
+    try:
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_catalogue(ctx, None, None, 1)
+        assert e.value.status == fof.FOF_ERR_BAD_STATE       # nothing built yet
+        for bad in (0, -3):
+            with pytest.raises(fof.FoFError) as e:
+                fof.fof_catalogue(ctx, None, None, bad)
+            assert e.value.status == fof.FOF_ERR_INVALID_ARG
+    finally:
+        fof.fof_destroy(ctx)
+
+
 def test_kernel_times_need_the_option():
     ctx = _ctx()
     try:

@@ -211,6 +211,47 @@ def test_dense_cells_premerged_by_sub_cells():
                 assert_single(pos, 0.004, strict=strict, predicate=predicate, cell_factor=cf, dense_min=8)
 
 
+def _catalogue_reference(label, size, offsets, min_size):
+    idx = np.flatnonzero(size >= min_size)
+    box = np.searchsorted(np.asarray(offsets), idx, side="right") - 1
+    return label[idx], size[idx], box
+
+
+def test_group_catalogue():
+    n = 120000
+    pos = synth.clustered(n, 37, 0, 0.7)
+    lx = synth.linking_length(0.2, n)
+    ref = oracle.fof(pos, lx)
+    w = synth.make("batched256", n_boxes=20, size_scale=0.05)
+    sizes = np.diff(w.offsets)
+    sizes[4] = 0                                   # an empty box
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    bpos = np.concatenate([w.pos[w.offsets[k]:w.offsets[k] + sizes[k]] for k in range(20)])
+    bref = oracle.fof_boxes(bpos, offsets, w.box, w.lx)
+    for p_np, off, L, l, r in ((pos, [0, n], 1.0, lx, ref), (bpos, offsets, w.box, w.lx, bref)):
+        f = fof.FoF()
+        try:
+            p = torch.from_numpy(np.ascontiguousarray(p_np)).cuda()
+            label, size, ng = f.run(p, off, L, l)
+            assert np.array_equal(label.cpu().numpy(), r[0])
+            for min_size in (1, 2, 20, 10 ** 9):
+                first, gsize, gbox = (t.cpu().numpy() for t in f.catalogue(label, size, min_size))
+                e_first, e_size, e_box = _catalogue_reference(r[0], r[1], off, min_size)
+                assert np.array_equal(first, e_first) and np.array_equal(gsize, e_size)
+                assert np.array_equal(gbox, e_box)
+                if min_size == 1:   # every group once: the sizes add up to N, one entry per group
+                    assert int(gsize.sum()) == len(p_np) and len(first) == int(np.sum(ng))
+            # a capacity below the count: the count is still exact, the first entries are written
+            full = fof.fof_catalogue(f.ctx, label, size, 2)
+            cap = max(1, full // 3)
+            a, b_, c = (torch.full((cap,), -7, dtype=torch.int32, device="cuda") for _ in range(3))
+            assert fof.fof_catalogue(f.ctx, label, size, 2, a, b_, c, cap) == full
+            e_first, e_size, e_box = _catalogue_reference(r[0], r[1], off, 2)
+            assert np.array_equal(a.cpu().numpy(), e_first[:cap]) and np.array_equal(b_.cpu().numpy(), e_size[:cap])
+        finally:
+            f.close()
+
+
 def test_uniform32k_and_strict():
     w = synth.make("uniform32k")
     for predicate in PREDICATES:
