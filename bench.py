@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--dense-min", type=int, default=None, help="skip tuning, use this dense threshold")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-domains", action="store_true")
+    ap.add_argument("--domains", type=int, default=8, help="slabs of the domain-decomposed measurement")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (a known-size kernel whose "
@@ -273,6 +275,26 @@ def main():
     st = fs.stats()
     fs.close()
 
+    # --- domain-decomposed merge (slabs along x, global merge of the links
+    #     across them) on the same workload and configuration ----------------
+    domain = None
+    if not args.no_domains:
+        log("timing domain-decomposed merge")
+        fd = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"], timings=True,
+                     domains=args.domains)
+        ld, sd = fd.outputs(n)
+        msd, _ = timed_steps(torch, fof, fd, pos, w, max(3, args.steps // 2), 1, ld, sd)
+        fd.close()
+        fds = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"], stats=True,
+                      domains=args.domains)
+        fds.run(pos, w.offsets, w.box, w.lx)
+        std = fds.stats()
+        fds.close()
+        domain = {"domains": args.domains, "value": n / (msd * 1e-3), "ms_per_step": msd,
+                  "boundary_links": std["boundary_links"], "boundary_groups": std["boundary_groups"],
+                  "exact_vs_single_domain": bool(np.array_equal(ld.cpu().numpy(), lab32)
+                                                 and np.array_equal(sd.cpu().numpy(), size32))}
+
     # --- plain FP64 on the same workload -----------------------------------
     plain = None
     exact = None
@@ -415,6 +437,7 @@ def main():
         "plain_fp64": plain,
         "exact_fp32_vs_fp64": exact,
         "batched": batched,
+        "domain_decomposed": domain,
         "cpu_baseline": cpu,
         "exact_vs_oracle_on_sample": sample_exact,
     }

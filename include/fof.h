@@ -84,7 +84,12 @@ typedef struct {
     int32_t sort_segment_log2; /* the cell sort counts cells in on-chip memory, 2^k cells per
                                 work-group: k in 6..14; 0 = automatic (about 1.4k particles per
                                 work-group on average). Changes speed only */
-    int32_t reserved[4];     /* must be zero */
+    int32_t domains;         /* > 1: domain-decomposed merge on one GPU (paper, Section 3.3): every box
+                                is cut into this many slabs along x; union-find runs on the links
+                                inside each slab, links across slabs are collected, their groups are
+                                numbered densely and merged by a second union-find, and the roots are
+                                updated. Same labels as without; at most 4096. 0 or 1 = off */
+    int32_t reserved[3];     /* must be zero */
 } fof_options;
 
 typedef struct {
@@ -99,7 +104,9 @@ typedef struct {
     int64_t sparse_pair_tests; /* of pair_tests, those made by the per-particle search (collect_stats only) */
     int64_t queued_links;    /* linked pairs queued for the deferred union pass */
     int64_t dense_items;     /* wavefront work items (64 particles of a dense cell each) */
-    int64_t reserved[5];
+    int64_t boundary_links;  /* domain mode: linked pairs across slabs (the exchanged link list) */
+    int64_t boundary_groups; /* domain mode: distinct slab-local groups in that list */
+    int64_t reserved[3];
 } fof_stats;
 
 /* Geometry and FP32 decision thresholds the library uses for one box. */

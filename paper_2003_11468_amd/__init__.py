@@ -38,7 +38,8 @@ class FoFError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("predicate", ctypes.c_int32), ("strict_less", ctypes.c_int32), ("cell_factor", ctypes.c_double),
                 ("collect_stats", ctypes.c_int32), ("dense_min", ctypes.c_int32), ("collect_timings", ctypes.c_int32),
-                ("sort_segment_log2", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("sort_segment_log2", ctypes.c_int32), ("domains", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -46,7 +47,8 @@ class Stats(ctypes.Structure):
                 ("pair_tests", ctypes.c_int64), ("links", ctypes.c_int64), ("band_hits", ctypes.c_int64),
                 ("cas_retries", ctypes.c_int64), ("fp64_boxes", ctypes.c_int64),
                 ("sparse_pair_tests", ctypes.c_int64), ("queued_links", ctypes.c_int64),
-                ("dense_items", ctypes.c_int64), ("reserved", ctypes.c_int64 * 5)]
+                ("dense_items", ctypes.c_int64), ("boundary_links", ctypes.c_int64),
+                ("boundary_groups", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -253,9 +255,11 @@ def fof_status_string(status: int) -> str:
 # ------------------------------------------------------ tensor wrapper --
 
 def make_options(predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
-                 stats: bool = False, dense_min: int = 0, timings: bool = False, segment_log2: int = 0) -> Options:
+                 stats: bool = False, dense_min: int = 0, timings: bool = False, segment_log2: int = 0,
+                 domains: int = 0) -> Options:
     o = fof_default_options()
     o.sort_segment_log2 = int(segment_log2)
+    o.domains = int(domains)
     o.collect_timings = int(timings)
     o.predicate = PREDICATES[predicate]
     o.strict_less = int(strict)
@@ -270,13 +274,13 @@ class FoF:
 
     def __init__(self, predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
                  stats: bool = False, stream=None, dense_min: int = 0, timings: bool = False,
-                 segment_log2: int = 0):
+                 segment_log2: int = 0, domains: int = 0):
         import torch
 
         self._torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats, dense_min, timings, segment_log2),
-                              self.stream.cuda_stream)
+        self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats, dense_min, timings, segment_log2,
+                                           domains), self.stream.cuda_stream)
         self.ws = None
 
     def close(self):

@@ -20,6 +20,7 @@ using fof::Plan;
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxCells = (int64_t)INT32_MAX - 2;
+constexpr int kMaxDomains = 4096;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -55,7 +56,7 @@ struct HostPlan {
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_kmap = 0, o_sorted = 0,
            o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
            o_stpos = 0, o_wave_roots = 0, o_occ = 0, o_edge_fill = 0, o_seg = 0, o_staging2 = 0,
-           o_stage2_k = 0, total = 0;
+           o_stage2_k = 0, o_bnd = 0, total = 0;
     int64_t max_edges = 0;
 
     bool same_geometry(const HostPlan &o) const
@@ -145,7 +146,8 @@ bool options_valid(const fof_options &o)
     if (o.collect_timings != 0 && o.collect_timings != 1) return false;
     if (o.sort_segment_log2 != 0 && (o.sort_segment_log2 < fof::kSegLog2Min || o.sort_segment_log2 > fof::kSegLog2Max))
         return false;
-    for (int k = 0; k < 4; ++k)
+    if (o.domains < 0 || o.domains > kMaxDomains) return false;
+    for (int k = 0; k < 3; ++k)
         if (o.reserved[k] != 0) return false;
     return true;
 }
@@ -279,6 +281,10 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
         const int64_t t = fof::scan_scratch_for(p.n_tiles + 1);   // the group catalogue
         p.scan_tiles = a > b ? a : b;
         if (t > p.scan_tiles) p.scan_tiles = t;
+        if (c->opt.domains > 1) {   // the global merge numbers the groups of the boundary links
+            const int64_t g = fof::scan_scratch_for(offsets[n_boxes] + 1);
+            if (g > p.scan_tiles) p.scan_tiles = g;
+        }
     }
     if ((int64_t)p.n_buckets * p.n_tiles > (int64_t)INT32_MAX) return FOF_ERR_UNSUPPORTED;
 
@@ -316,6 +322,7 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.o_seg = take(sizeof(int32_t) * (size_t)p.n_segments);
     p.o_staging2 = take(sizeof(float) * 4 * n);
     p.o_stage2_k = take(sizeof(int32_t) * n);
+    p.o_bnd = c->opt.domains > 1 ? take(sizeof(int32_t) * 2 * (size_t)p.max_edges) : 0;
     p.total = o;
     *out = std::move(p);
     return FOF_OK;
@@ -384,6 +391,7 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.dense_min = dense_min_of(c->opt);
     d.dense_blocks = kDenseBlocks;
     d.sparse_blocks = kSparseBlocks;
+    d.domains = c->opt.domains > 1 ? c->opt.domains : 0;
     d.max_items = p.max_items;
     d.max_edges = p.max_edges;
     d.box0 = p.boxes[0];
@@ -400,6 +408,7 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.gsize = at<int32_t>(c->ws, p.o_gsize);
     d.items = at<int4>(c->ws, p.o_items);
     d.edges = at<int2>(c->ws, p.o_edges);
+    d.bnd = c->opt.domains > 1 ? at<int2>(c->ws, p.o_bnd) : nullptr;
     d.bucket_hist = at<int32_t>(c->ws, p.o_hist);
     d.staging = at<float4>(c->ws, p.o_staging);
     d.stpos = at<int32_t>(c->ws, p.o_stpos);
@@ -596,6 +605,8 @@ fof_status fof_get_stats(fof_ctx *ctx, fof_stats *out)
     out->sparse_pair_tests = (int64_t)cnt.sparse_tests;
     out->queued_links = (int64_t)cnt.n_edges;
     out->dense_items = (int64_t)cnt.n_items;
+    out->boundary_links = (int64_t)cnt.n_boundary;
+    out->boundary_groups = (int64_t)cnt.n_bgroups;
     return st;
 }
 

@@ -36,7 +36,9 @@ struct Counters {
     unsigned int error;         // bit 0: coordinate outside [0, L) or not finite; bit 1: sort inconsistency
     unsigned int n_items;       // work items of the dense link kernel
     unsigned int n_edges;       // linked pairs queued for the union kernel (summed after the search)
-    unsigned int pad[5];
+    unsigned int n_boundary;    // domain mode: linked pairs across domains (may exceed the list's capacity)
+    unsigned int n_bgroups;     // domain mode: distinct local groups met by those pairs
+    unsigned int pad[3];
 };
 
 // Everything a launch needs: raw pointers into the caller's workspace.
@@ -57,6 +59,8 @@ struct Plan {
     int32_t dense_min;      // cells with at least this many particles use the wave kernel
     int32_t dense_blocks;   // grid of the persistent dense link kernel
     int32_t sparse_blocks;  // grid of the persistent sparse link kernel
+    int32_t domains;        // > 1: slabs along x, local union-find per slab, then a global merge
+    int32_t pad1;
     int64_t max_items;      // capacity of `items`
     int64_t max_edges;      // capacity of `edges`: kEdgeSlices slices of max_edges / kEdgeSlices
 
@@ -84,6 +88,7 @@ struct Plan {
     int32_t *gsize;         // [n] group member count at roots (sorted indices)
     int4 *items;            // [max_items] dense work: {cell, first home particle, box, 0}
     int2 *edges;            // [max_edges] linked pairs found by the sparse search
+    int2 *bnd;              // domain mode: [max_edges] linked pairs across domains, then their root pairs
     unsigned int *edge_fill;   // [kEdgeSlices] pairs appended to each slice (may exceed its capacity)
     unsigned long long *n_groups;  // [n_boxes]
     Counters *counters;
@@ -126,6 +131,9 @@ struct KernelTimer {
 hipError_t launch_clear(const Plan &p, hipStream_t stream, KernelTimer *t);
 hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t);
 hipError_t launch_link(const Plan &p, hipStream_t stream, KernelTimer *t);
+// Exclusive prefix sum of data[0, len) in place (fof_kernels.hip); scratch
+// holds scan_scratch_for(len) ints.
+void scan_exclusive(int *data, int64_t len, int *scratch, hipStream_t stream);
 hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t);
 // Groups of at least min_size members (fof_kernels.hip); the total is left in
 // p.bucket_hist[p.n_tiles].

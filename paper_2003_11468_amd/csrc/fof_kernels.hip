@@ -66,6 +66,8 @@ __global__ void __launch_bounds__(kBlock) k_clear(Plan p)
         p.counters->error = 0;
         p.counters->n_items = 0;
         p.counters->n_edges = 0;
+        p.counters->n_boundary = 0;
+        p.counters->n_bgroups = 0;
     }
 }
 
@@ -701,6 +703,8 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 constexpr int64_t kStreamBlocks = 2048;
 inline int64_t grid_tiles(int64_t n) { return (n + kBlock - 1) / kBlock; }
 
+}  // namespace
+
 // Exclusive scan of data[0, len) in place; `scratch` holds the tile sums of
 // every level (scan_scratch_for(len) ints).
 void scan_exclusive(int *data, int64_t len, int *scratch, hipStream_t stream)
@@ -715,7 +719,6 @@ void scan_exclusive(int *data, int64_t len, int *scratch, hipStream_t stream)
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(kBlock), 0, stream, a);
 }
 
-}  // namespace
 
 // Launch bracketed by the timer marks.
 #define FOF_TIMED(id, ...)                 \

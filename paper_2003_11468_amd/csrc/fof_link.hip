@@ -61,6 +61,45 @@ __device__ __forceinline__ int unite_root(int *parent, int a, int b, unsigned &r
     }
 }
 
+constexpr unsigned kGlobalMergeBlocks = 2048;
+
+// ------------------------------------------------------ domain decomposition --
+// Domain mode (paper, Section 3.3, on one GPU): a box is cut into `domains`
+// slabs along x. Union-find merges only links inside a slab; a link across
+// slabs goes to the boundary list (the list the paper's ranks exchange), and
+// the global merge after the search joins the groups it names.
+
+// Slab of a particle at x in a box of side L.
+__device__ __forceinline__ int slab_of(float x, int domains, double L)
+{
+    const int d = (int)((double)x * (double)domains / L);
+    return d < domains ? d : domains - 1;
+}
+
+// Slab of sorted particle s.
+__device__ __forceinline__ int domain_of(const Plan &p, int s)
+{
+    const int b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, s);
+    return slab_of(p.sorted[s].x, p.domains, box_of(p, b).L);
+}
+
+// Appends the pair to the boundary list; a pair that finds the list full is
+// merged at once (the groups come out the same).
+__device__ __forceinline__ void defer_boundary(const Plan &p, int a, int b, unsigned &retries)
+{
+    const unsigned at = atomicAdd(&p.counters->n_boundary, 1u);
+    if ((int64_t)at < p.max_edges) p.bnd[at] = make_int2(a, b);
+    else retries += unite(p.parent, a, b);
+}
+
+// Merge of a linked pair found by the search: at once, or in domain mode
+// through the boundary list when the pair crosses slabs.
+__device__ __forceinline__ void merge_pair(const Plan &p, int a, int b, unsigned &retries)
+{
+    if (p.domains > 1 && domain_of(p, a) != domain_of(p, b)) defer_boundary(p, a, b, retries);
+    else retries += unite(p.parent, a, b);
+}
+
 // --------------------------------------------------------- sparse (lane) --
 
 // Periodic shift code of one axis for a candidate range: 0 none; 1 the
@@ -162,7 +201,7 @@ struct EdgeSink {
             const int2 e = buf[k];
             const int64_t at = (int64_t)base + k;
             if (at < cap) p.edges[slice * cap + at] = e;
-            else retries += unite(p.parent, e.x, e.y);
+            else merge_pair(p, e.x, e.y, retries);
         }
         __builtin_amdgcn_wave_barrier();
         count = 0;
@@ -443,7 +482,7 @@ __global__ void __launch_bounds__(kBlock) k_union_edges(Plan p)
     unsigned retries = 0;
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < ne; k += (int64_t)gridDim.x * kBlock) {
         const int2 e = edges[k];
-        retries += unite(p.parent, e.x, e.y);
+        merge_pair(p, e.x, e.y, retries);
     }
     if (kStats) {
         unsigned long long r = wave_sum_u64((unsigned long long)retries);
@@ -506,7 +545,11 @@ __device__ __forceinline__ void dense_hit(const Plan &p, const BoxRegs &br, cons
         int rj;
         if constexpr (kFP64) rj = st.root[kk];
         else rj = __float_as_int(st.v[kk].w);
-        if (rj != root_i) root_i = unite_root(p.parent, root_i, rj, retries);
+        if (rj != root_i) {
+            if (p.domains > 1 && domain_of(p, j) != slab_of(pi.x, p.domains, br.L))
+                defer_boundary(p, root_i, rj, retries);
+            else root_i = unite_root(p.parent, root_i, rj, retries);
+        }
     }
 }
 
@@ -728,6 +771,81 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
     }
 }
 
+// Global merge of domain mode, after the search. Workspace: the segment-order
+// staging buffer (free after the build) holds flag/number [n + 1], the
+// merge forest [n] and the group of each number [n].
+//   roots: replace each boundary pair by the roots of its two groups and flag them
+//   (an exclusive prefix over the flags numbers the flagged groups densely:
+//    the paper's global-ID map, order-preserving so the smallest root of a
+//    merged set also has the smallest number)
+//   init:  a one-node tree per numbered group
+//   union: union-find over the numbered pairs
+//   apply: hook each merged group's root under its set's smallest root
+__device__ __forceinline__ int *gm_flag(const Plan &p) { return reinterpret_cast<int *>(p.staging2); }
+__device__ __forceinline__ int *gm_parent(const Plan &p) { return gm_flag(p) + p.n + 1; }
+__device__ __forceinline__ int *gm_group(const Plan &p) { return gm_flag(p) + 2 * p.n + 1; }
+__device__ __forceinline__ int64_t gm_pairs(const Plan &p)
+{
+    const int64_t nb = p.counters->n_boundary;
+    return nb < p.max_edges ? nb : p.max_edges;
+}
+
+__global__ void __launch_bounds__(kBlock) k_gm_clear(Plan p)
+{
+    int *flag = gm_flag(p);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i <= p.n; i += (int64_t)gridDim.x * kBlock) flag[i] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_gm_roots(Plan p)
+{
+    int *flag = gm_flag(p);
+    const int64_t nb = gm_pairs(p);
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nb; k += (int64_t)gridDim.x * kBlock) {
+        const int2 e = p.bnd[k];
+        const int ra = find_halve(p.parent, e.x), rb = find_halve(p.parent, e.y);
+        p.bnd[k] = make_int2(ra, rb);
+        flag[ra] = 1;
+        flag[rb] = 1;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_gm_init(Plan p)
+{
+    const int *num = gm_flag(p);   // exclusive prefix of the flags
+    int *gp = gm_parent(p), *grp = gm_group(p);
+    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < p.n; r += (int64_t)gridDim.x * kBlock) {
+        const int k = num[r];
+        if (num[r + 1] != k) {
+            gp[k] = k;
+            grp[k] = (int)r;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.counters->n_bgroups = (unsigned)num[p.n];
+}
+
+__global__ void __launch_bounds__(kBlock) k_gm_union(Plan p)
+{
+    const int *num = gm_flag(p);
+    int *gp = gm_parent(p);
+    const int64_t nb = gm_pairs(p);
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nb; k += (int64_t)gridDim.x * kBlock) {
+        const int2 e = p.bnd[k];
+        (void)unite(gp, num[e.x], num[e.y]);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_gm_apply(Plan p)
+{
+    const int *num = gm_flag(p);
+    int *gp = gm_parent(p);
+    const int *grp = gm_group(p);
+    const int m = num[p.n];
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < m; k += gridDim.x * kBlock) {
+        const int r = find_halve(gp, k);
+        if (r != k) p.parent[grp[k]] = grp[r];   // grp[r] < grp[k]: numbers keep the order of the roots
+    }
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <bool kFP64, bool kStats>
@@ -740,9 +858,23 @@ void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
     hipLaunchKernelGGL((k_union_edges<kStats>), dim3(16, kEdgeSlices), dim3(kBlock), 0, stream, p);
     if (t) t->mark(K_UNION_EDGES, true, stream);
     if (t) t->mark(K_LINK_DENSE, false, stream);
-    hipLaunchKernelGGL(k_dense_premerge, dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
+    // the sub-cell pre-merge would merge across slab faces: not in domain mode
+    if (p.domains <= 1)
+        hipLaunchKernelGGL(k_dense_premerge, dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
     hipLaunchKernelGGL((k_link_dense<kFP64, kStats>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
     if (t) t->mark(K_LINK_DENSE, true, stream);
+    if (p.domains > 1) {
+        // global merge, timed with the union pass
+        if (t) t->mark(K_UNION_EDGES, false, stream);
+        const unsigned g = kGlobalMergeBlocks;
+        hipLaunchKernelGGL(k_gm_clear, dim3(g), dim3(kBlock), 0, stream, p);
+        hipLaunchKernelGGL(k_gm_roots, dim3(g), dim3(kBlock), 0, stream, p);
+        scan_exclusive(reinterpret_cast<int *>(p.staging2), p.n + 1, p.scan_part, stream);
+        hipLaunchKernelGGL(k_gm_init, dim3(g), dim3(kBlock), 0, stream, p);
+        hipLaunchKernelGGL(k_gm_union, dim3(g), dim3(kBlock), 0, stream, p);
+        hipLaunchKernelGGL(k_gm_apply, dim3(g), dim3(kBlock), 0, stream, p);
+        if (t) t->mark(K_UNION_EDGES, true, stream);
+    }
 }
 
 }  // namespace

@@ -41,7 +41,7 @@ def _ctx(**kw):
 
 def test_create_rejects_bad_options():
     for kw in (dict(cell_factor=0.5), dict(cell_factor=float("inf")), dict(segment_log2=5), dict(segment_log2=15),
-               dict(segment_log2=-1)):
+               dict(segment_log2=-1), dict(domains=-1), dict(domains=4097)):
         with pytest.raises(fof.FoFError) as e:
             _ctx(**kw)
         assert e.value.status == fof.FOF_ERR_INVALID_ARG
@@ -50,7 +50,7 @@ def test_create_rejects_bad_options():
     with pytest.raises(fof.FoFError):
         fof.fof_create(o)
     o = fof.fof_default_options()
-    o.reserved[3] = 1
+    o.reserved[2] = 1
     with pytest.raises(fof.FoFError):
         fof.fof_create(o)
 

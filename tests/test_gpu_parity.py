@@ -21,8 +21,9 @@ PREDICATES = ["fp32_filter", "fp64"]
 
 
 def gpu_run(pos, offsets, box, lx, predicate="fp32_filter", strict=False, cell_factor=0.0, stats=False,
-            dense_min=0, segment_log2=0):
-    f = fof.FoF(predicate, strict, cell_factor, stats, dense_min=dense_min, segment_log2=segment_log2)
+            dense_min=0, segment_log2=0, domains=0):
+    f = fof.FoF(predicate, strict, cell_factor, stats, dense_min=dense_min, segment_log2=segment_log2,
+                domains=domains)
     try:
         p = torch.from_numpy(np.ascontiguousarray(pos, dtype=np.float32)).cuda()
         label, size, ng = f.run(p, offsets, box, lx)
@@ -250,6 +251,33 @@ def test_group_catalogue():
             assert np.array_equal(a.cpu().numpy(), e_first[:cap]) and np.array_equal(b_.cpu().numpy(), e_size[:cap])
         finally:
             f.close()
+
+
+# Domain-decomposed merge on one GPU (Section 3.3): union-find inside slabs
+# along x, the links across slabs collected, their groups numbered densely and
+# merged. The labels must not change; the boundary list must be in use.
+@pytest.mark.parametrize("domains", [2, 3, 7, 16])
+def test_domain_decomposed_merge(domains):
+    n = 150000
+    pos = synth.clustered(n, 43, 0, 0.7)
+    for b, cf, dm in ((0.2, 2.0, 32), (0.5, 1.0, 8), (0.9, 0.0, 4)):
+        lx = synth.linking_length(b, n)
+        ref = oracle.fof(pos, lx)
+        for predicate in PREDICATES:
+            lab, size, ng, st = gpu_run(pos, [0, n], 1.0, lx, predicate, cell_factor=cf, dense_min=dm, stats=True,
+                                        domains=domains)
+            assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and int(ng[0]) == ref[2]
+            assert st["boundary_links"] > 0 and 0 < st["boundary_groups"] <= 2 * st["boundary_links"]
+    for axis in range(3):   # chains across each periodic face, the x face being a slab face too
+        pc = chain_across_boundary(40, 0.0234375, axis)
+        ref = oracle.fof(pc, 0.03125)
+        lab, size, ng, _ = gpu_run(pc, [0, len(pc)], 1.0, 0.03125, domains=domains)
+        assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1])
+    w = synth.make("batched256", n_boxes=12, size_scale=0.05)
+    ref = oracle.fof_boxes(w.pos, w.offsets, w.box, w.lx)
+    for predicate in PREDICATES:
+        lab, size, ng, _ = gpu_run(w.pos, w.offsets, w.box, w.lx, predicate, dense_min=16, domains=domains)
+        assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and np.array_equal(ng, ref[2])
 
 
 def test_uniform32k_and_strict():
