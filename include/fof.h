@@ -122,6 +122,19 @@ typedef struct {
     int32_t reserved[2];
 } fof_box_info;
 
+/* Re-links the particles of the last successful fof_build_cells with new
+ * linking lengths h_lx[0 .. n_boxes-1] (one per box, as many boxes as that
+ * build) without rebuilding the cells, as an on-the-fly group finder inside
+ * a simulation would reuse its cell structure (paper, Section 1). Each new
+ * l_x must be at most the l_x the cells were built for (the cells stay at
+ * least l_x (1 + 2^-20) wide); the FP32 thresholds are recomputed. Allowed
+ * after fof_build_cells, fof_link or fof_finalize; resets the forest, after
+ * which fof_link and fof_finalize run as usual. Enqueues on the context's
+ * stream. Errors: FOF_ERR_INVALID_ARG (null, count differs from the build, an
+ * l_x not positive or larger than the build's), FOF_ERR_BAD_STATE (no
+ * successful build on this context), FOF_ERR_DEVICE. */
+fof_status fof_relink(fof_ctx *ctx, const double *h_lx, int32_t n_boxes);
+
 /* Group catalogue (the step after labelling; the paper's group-size pass,
  * Section 3.4.1-3.4.2, and its catalogue of groups above a size cut): the
  * groups of at least `min_size` members of the outputs of the last

@@ -64,7 +64,7 @@ _lib = None
 EXPORTS = ["fof_default_options", "fof_create", "fof_set_stream", "fof_workspace_bytes", "fof_set_workspace",
            "fof_build_cells", "fof_link", "fof_finalize", "fof_read_n_groups", "fof_get_stats",
            "fof_graph_capture", "fof_graph_launch", "fof_destroy", "fof_status_string", "fof_get_kernel_times",
-           "fof_kernel_name", "fof_describe_box", "fof_catalogue"]
+           "fof_kernel_name", "fof_describe_box", "fof_catalogue", "fof_relink"]
 
 
 def load_library():
@@ -97,6 +97,7 @@ def load_library():
         "fof_describe_box": (ctypes.c_int, [ctypes.POINTER(Options), i64, ctypes.c_double, ctypes.c_double,
                                             ctypes.POINTER(BoxInfo)]),
         "fof_catalogue": (ctypes.c_int, [vp, vp, vp, i32, vp, vp, vp, i64, i64p]),
+        "fof_relink": (ctypes.c_int, [vp, f64p, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -244,6 +245,13 @@ def fof_catalogue(ctx, label, size, min_size: int, first=None, gsize=None, gbox=
     return int(count.value)
 
 
+def fof_relink(ctx, lx, n_boxes: int):
+    """New linking lengths (one per box, each at most the build's) over the built cells."""
+    l = _arr(np.broadcast_to(np.asarray(lx, dtype=np.float64), (int(n_boxes),)), np.float64)
+    _check(load_library().fof_relink(ctx, l.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_boxes)),
+           "fof_relink")
+
+
 def fof_kernel_name(k: int) -> str:
     return load_library().fof_kernel_name(k).decode()
 
@@ -312,6 +320,7 @@ class FoF:
         self.reserve(offsets, box, lx)
         if label is None or size is None:
             label, size = self.outputs(pos.shape[0])
+        self._n = pos.shape[0]
         fof_build_cells(self.ctx, pos, offsets, box, lx)
         fof_link(self.ctx)
         ng = fof_finalize(self.ctx, label, size, len(offsets) - 1 if sync else None)
@@ -333,6 +342,16 @@ class FoF:
 
     def kernel_times(self) -> dict:
         return fof_get_kernel_times(self.ctx)
+
+    def relink(self, lx, n_boxes: int, label=None, size=None, sync: bool = True):
+        """Groups at new linking lengths (each at most the last build's) over the cells of the
+        last run. Returns (label, size, n_groups or None) like run()."""
+        if label is None or size is None:
+            label, size = self.outputs(int(self._n))
+        fof_relink(self.ctx, lx, n_boxes)
+        fof_link(self.ctx)
+        ng = fof_finalize(self.ctx, label, size, n_boxes if sync else None)
+        return label, size, ng
 
     def catalogue(self, label, size, min_size: int = 1):
         """(first, size, box) tensors of the groups of at least min_size members of the

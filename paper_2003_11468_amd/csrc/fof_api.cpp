@@ -52,6 +52,7 @@ struct HostPlan {
     int64_t max_items = 0;
     std::vector<BoxDev> boxes;
     std::vector<int64_t> p0;
+    std::vector<double> lx_cells;   // linking length each box's cells were sized for
     // workspace layout (byte offsets)
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_kmap = 0, o_sorted = 0,
            o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
@@ -126,6 +127,7 @@ struct fof_ctx {
     size_t stage_bytes = 0;
 
     int state = 0;             // 0 idle, 1 cells built, 2 linked
+    bool cells_valid = false;  // the last build's cells and sorted positions are in the workspace
     Plan dev{};                // pointers of the current run
 
     hipGraph_t graph = nullptr;
@@ -243,6 +245,7 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
         b.half = 0.5 * L;
         b.inv_h = (double)nc / L;
         b.l2 = l * l;
+        p.lx_cells.push_back(l);
         fp32_thresholds(b, l);
         b.sub_k = sub_cells_per_axis(L, nc, l);
         if (c->opt.predicate == FOF_PRED_FP32_FILTER && b.use_fp64) ++p.fp64_boxes;
@@ -343,6 +346,27 @@ T *at(void *base, size_t off)
     return reinterpret_cast<T *>(static_cast<char *>(base) + off);
 }
 
+// Copies the box table and offsets of `np` to the start of the workspace.
+fof_status upload_table(fof_ctx *c, const HostPlan &np)
+{
+    const size_t table = np.o_counters;   // boxes + p0 region
+    // the staging buffer may still feed an earlier, in-flight copy
+    if (c->stage && hipStreamSynchronize(c->stream) != hipSuccess) return FOF_ERR_DEVICE;
+    if (c->stage_bytes < table) {
+        if (c->stage) (void)hipHostFree(c->stage);
+        c->stage = nullptr;
+        c->stage_bytes = 0;
+        if (hipHostMalloc(&c->stage, table, hipHostMallocDefault) != hipSuccess) return FOF_ERR_DEVICE;
+        c->stage_bytes = table;
+    }
+    std::memset(c->stage, 0, table);
+    std::memcpy(at<char>(c->stage, np.o_boxes), np.boxes.data(), sizeof(BoxDev) * np.boxes.size());
+    std::memcpy(at<char>(c->stage, np.o_p0), np.p0.data(), sizeof(int64_t) * np.p0.size());
+    if (hipMemcpyAsync(c->ws, c->stage, table, hipMemcpyHostToDevice, c->stream) != hipSuccess) return FOF_ERR_DEVICE;
+    c->uploaded = true;
+    return FOF_OK;
+}
+
 // Adopt `np` as the current plan; upload its descriptor table if it changed.
 fof_status install_plan(fof_ctx *c, HostPlan &&np)
 {
@@ -353,22 +377,8 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     // a single box travels in the kernel arguments: nothing to upload
     const bool same = np.n_boxes == 1 || (c->planned && c->uploaded && c->plan.same_geometry(np));
     if (!same) {
-        const size_t table = np.o_counters;   // boxes + p0 region
-        // the staging buffer may still feed an earlier, in-flight copy
-        if (c->stage && hipStreamSynchronize(c->stream) != hipSuccess) return FOF_ERR_DEVICE;
-        if (c->stage_bytes < table) {
-            if (c->stage) (void)hipHostFree(c->stage);
-            c->stage = nullptr;
-            c->stage_bytes = 0;
-            if (hipHostMalloc(&c->stage, table, hipHostMallocDefault) != hipSuccess) return FOF_ERR_DEVICE;
-            c->stage_bytes = table;
-        }
-        std::memset(c->stage, 0, table);
-        std::memcpy(at<char>(c->stage, np.o_boxes), np.boxes.data(), sizeof(BoxDev) * np.boxes.size());
-        std::memcpy(at<char>(c->stage, np.o_p0), np.p0.data(), sizeof(int64_t) * np.p0.size());
-        hipError_t e = hipMemcpyAsync(c->ws, c->stage, table, hipMemcpyHostToDevice, c->stream);
-        if (e != hipSuccess) return FOF_ERR_DEVICE;
-        c->uploaded = true;
+        st = upload_table(c, np);
+        if (st != FOF_OK) return st;
     }
     c->plan = std::move(np);
     c->planned = true;
@@ -528,9 +538,38 @@ fof_status fof_build_cells(fof_ctx *ctx, const float *d_pos, const int64_t *h_bo
                            const double *h_lx, int32_t n_boxes)
 {
     if (!ctx) return FOF_ERR_INVALID_ARG;
+    ctx->cells_valid = false;
     fof_status st = do_build(ctx, d_pos, h_box_offsets, h_box, h_lx, n_boxes);
     if (st != FOF_OK) return st;
     st = enqueue_build(ctx, ctx->stream);
+    ctx->state = st == FOF_OK ? 1 : 0;
+    ctx->cells_valid = st == FOF_OK;
+    return st;
+}
+
+fof_status fof_relink(fof_ctx *ctx, const double *h_lx, int32_t n_boxes)
+{
+    if (!ctx || !h_lx) return FOF_ERR_INVALID_ARG;
+    if (!ctx->cells_valid || !ctx->planned) return FOF_ERR_BAD_STATE;
+    HostPlan &p = ctx->plan;
+    if (n_boxes != p.n_boxes) return FOF_ERR_INVALID_ARG;
+    for (int32_t k = 0; k < n_boxes; ++k)
+        if (!(h_lx[k] > 0.0) || !std::isfinite(h_lx[k]) || h_lx[k] > p.lx_cells[(size_t)k]) return FOF_ERR_INVALID_ARG;
+    p.fp64_boxes = 0;
+    for (int32_t k = 0; k < n_boxes; ++k) {
+        BoxDev &b = p.boxes[(size_t)k];
+        const double l = h_lx[k];
+        b.l2 = l * l;
+        fp32_thresholds(b, l);
+        b.sub_k = sub_cells_per_axis(b.L, b.nc, l);
+        if (ctx->opt.predicate == FOF_PRED_FP32_FILTER && b.use_fp64) ++p.fp64_boxes;
+    }
+    ctx->dev.box0 = p.boxes[0];
+    if (p.n_boxes > 1) {
+        fof_status st = upload_table(ctx, p);
+        if (st != FOF_OK) return st;
+    }
+    fof_status st = dev_err(fof::launch_relink_reset(ctx->dev, ctx->stream));
     ctx->state = st == FOF_OK ? 1 : 0;
     return st;
 }
@@ -614,6 +653,7 @@ fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_
                              const double *h_lx, int32_t n_boxes, int32_t *d_group_index, int32_t *d_group_size)
 {
     if (!ctx) return FOF_ERR_INVALID_ARG;
+    ctx->cells_valid = false;
     fof_status st = do_build(ctx, d_pos, h_box_offsets, h_box, h_lx, n_boxes);
     if (st != FOF_OK) return st;
     if ((!d_group_index || !d_group_size) && ctx->plan.n > 0) return FOF_ERR_INVALID_ARG;

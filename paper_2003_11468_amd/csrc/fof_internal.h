@@ -131,6 +131,9 @@ struct KernelTimer {
 hipError_t launch_clear(const Plan &p, hipStream_t stream, KernelTimer *t);
 hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t);
 hipError_t launch_link(const Plan &p, hipStream_t stream, KernelTimer *t);
+// A fresh forest over the built cells (fof_kernels.hip): parent, sizes, group
+// minima and the per-run counters reset, cells and dense work items kept.
+hipError_t launch_relink_reset(const Plan &p, hipStream_t stream);
 // Exclusive prefix sum of data[0, len) in place (fof_kernels.hip); scratch
 // holds scan_scratch_for(len) ints.
 void scan_exclusive(int *data, int64_t len, int *scratch, hipStream_t stream);

@@ -644,6 +644,31 @@ __global__ void __launch_bounds__(kBlock) k_gather(Plan p)
     p.size[i] = v.y;
 }
 
+// Relink: every particle its own group again; counters of the link and
+// finalize passes cleared (the dense item count of the build is kept).
+__global__ void __launch_bounds__(kBlock) k_relink_reset(Plan p)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < p.n; s += stride) {
+        p.parent[s] = (int)s;
+        p.gsize[s] = 1;
+        p.perm[s].y = p.perm[s].x;
+    }
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < p.n_boxes) p.n_groups[t] = 0;
+    if (t < kEdgeSlices) p.edge_fill[t] = 0;
+    if (t == 0) {
+        p.counters->pair_tests = 0;
+        p.counters->links = 0;
+        p.counters->band_hits = 0;
+        p.counters->cas_retries = 0;
+        p.counters->sparse_tests = 0;
+        p.counters->n_edges = 0;
+        p.counters->n_boundary = 0;
+        p.counters->n_bgroups = 0;
+    }
+}
+
 __global__ void k_clear_ints(int *a, int n)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = 0;
@@ -795,6 +820,16 @@ hipError_t launch_catalogue(const Plan &p, const int32_t *label, const int32_t *
     if (tiles)
         hipLaunchKernelGGL(k_cat_write, dim3(tiles), dim3(kBlock), 0, stream, p, label, size, min_size, count,
                            g_first, g_size, g_box, capacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_relink_reset(const Plan &p, hipStream_t stream)
+{
+    int64_t work = p.n > p.n_boxes ? p.n : p.n_boxes;
+    if (work < kEdgeSlices) work = kEdgeSlices;
+    unsigned g = grid_for(work);
+    if (g > 65536u) g = 65536u;
+    hipLaunchKernelGGL(k_relink_reset, dim3(g), dim3(kBlock), 0, stream, p);
     return hipGetLastError();
 }
 

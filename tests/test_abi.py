@@ -160,6 +160,17 @@ def test_catalogue_validation():
         fof.fof_destroy(ctx)
 
 
+def test_relink_needs_a_build():
+    ctx = _ctx()
+    try:
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_relink(ctx, 0.01, 1)
+        assert e.value.status == fof.FOF_ERR_BAD_STATE
+        assert fof.load_library().fof_relink(ctx, None, 1) == fof.FOF_ERR_INVALID_ARG
+    finally:
+        fof.fof_destroy(ctx)
+
+
 def test_kernel_times_need_the_option():
     ctx = _ctx()
     try:

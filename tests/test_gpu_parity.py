@@ -280,6 +280,42 @@ def test_domain_decomposed_merge(domains):
         assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and np.array_equal(ng, ref[2])
 
 
+# Relink: new linking lengths over the cells of the last build (each at most
+# the build's), several in a row, single box and batches, both predicates.
+def test_relink_reuses_the_cells():
+    n = 120000
+    pos = synth.clustered(n, 47, 0, 0.6)
+    lx0 = synth.linking_length(0.5, n)
+    p = torch.from_numpy(pos).cuda()
+    for predicate in PREDICATES:
+        f = fof.FoF(predicate, dense_min=16)
+        try:
+            label, size, ng = f.run(p, [0, n], 1.0, lx0)
+            ref = oracle.fof(pos, lx0)
+            assert np.array_equal(label.cpu().numpy(), ref[0])
+            for scale in (0.4, 1.0, 0.15, 0.8):
+                lab, sz, ng = f.relink(lx0 * scale, 1)
+                ref = oracle.fof(pos, lx0 * scale)
+                assert np.array_equal(lab.cpu().numpy(), ref[0]) and np.array_equal(sz.cpu().numpy(), ref[1])
+                assert int(ng[0]) == ref[2]
+            with pytest.raises(fof.FoFError) as e:      # cells too small for a longer linking length
+                fof.fof_relink(f.ctx, lx0 * 1.01, 1)
+            assert e.value.status == fof.FOF_ERR_INVALID_ARG
+        finally:
+            f.close()
+    w = synth.make("batched256", n_boxes=12, size_scale=0.05)
+    f = fof.FoF(dense_min=16)
+    try:
+        f.run(torch.from_numpy(w.pos).cuda(), w.offsets, w.box, w.lx)
+        lx1 = np.asarray(w.lx) * 0.6
+        lab, sz, ng = f.relink(lx1, w.n_boxes)
+        ref = oracle.fof_boxes(w.pos, w.offsets, w.box, lx1)
+        assert np.array_equal(lab.cpu().numpy(), ref[0]) and np.array_equal(sz.cpu().numpy(), ref[1])
+        assert np.array_equal(ng, ref[2])
+    finally:
+        f.close()
+
+
 def test_uniform32k_and_strict():
     w = synth.make("uniform32k")
     for predicate in PREDICATES:
