@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-domains", action="store_true")
+    ap.add_argument("--no-relink", action="store_true")
     ap.add_argument("--domains", type=int, default=8, help="slabs of the domain-decomposed measurement")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -278,7 +279,7 @@ def main():
     # --- relink: a shorter linking length (b = 0.16 instead of 0.2) over the
     #     cells of the same build, without rebuilding them ---------------------
     relink = None
-    if not args.no_domains:
+    if not args.no_relink:
         log("timing relink at b = 0.16")
         fr = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"])
         lr, sr = fr.outputs(n)
