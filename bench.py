@@ -11,7 +11,7 @@ one HIP graph) and the plain FP64 path are timed beside it and reported in
 the same JSON line, with per-kernel device times from HIP events recorded on
 the launch stream inside the timed region.
 
-Prints one JSON line. ``--gpus`` above 1 is refused: this build runs on one GPU.
+Prints one JSON line. ``--gpus`` above 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -228,8 +228,8 @@ def main():
         print(ingest_counters(args.ingest_counters), end="")
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on exactly one GPU (asked for --gpus {args.gpus}); "
+              "sharding over several GPUs is not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -62,7 +62,7 @@ typedef enum {
     FOF_ERR_BAD_STATE = 3,     /* calls out of order (link before build, finalize before link) */
     FOF_ERR_WORKSPACE = 4,     /* workspace missing, too small or misaligned */
     FOF_ERR_DEVICE = 5,        /* a HIP runtime call failed, or a device-side consistency check */
-    FOF_ERR_UNSUPPORTED = 6    /* valid request this build cannot serve (e.g. too many cells) */
+    FOF_ERR_UNSUPPORTED = 6    /* valid request the library cannot serve (e.g. too many cells) */
 } fof_status;
 
 typedef enum {
