@@ -389,6 +389,7 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
 {
     __shared__ int cnt[(1 << kLog2) + (1 << (kLog2 - 5)) + 1];
     __shared__ unsigned short order[kOrderCap];
+    __shared__ unsigned short lcell[kOrderCap];   // cell (in the segment) of each particle, when P <= kOrderCap
     __shared__ int lds[kSegWaves];
     const int j = (int)blockIdx.x;
     const int seg_cells = 1 << p.seg_shift;
@@ -401,7 +402,8 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     for (int c = tid; c <= sentinel; c += kSegBlock) cnt[c] = 0;
     __syncthreads();
 
-    // 1. counts
+    // 1. counts (and, for a segment placed through LDS, each particle's cell)
+    const bool through_lds = P <= kOrderCap;
     for (int k0 = a + tid; k0 < e; k0 += kSegUnroll * kSegBlock) {
         float4 v[kSegUnroll];
 #pragma unroll
@@ -409,7 +411,11 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
             if (k0 + q * kSegBlock < e) v[q] = p.staging2[k0 + q * kSegBlock];
 #pragma unroll
         for (int q = 0; q < kSegUnroll; ++q)
-            if (k0 + q * kSegBlock < e) atomicAdd(&cnt[pad_idx(staged_cell(p, v[q]) - cell0)], 1);
+            if (k0 + q * kSegBlock < e) {
+                const int c = staged_cell(p, v[q]) - cell0;
+                atomicAdd(&cnt[pad_idx(c)], 1);
+                if (through_lds) lcell[k0 + q * kSegBlock - a] = (unsigned short)c;
+            }
     }
     __syncthreads();
 
@@ -465,10 +471,16 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     }
     __syncthreads();
 
-    // 4. placement
-    const bool through_lds = P <= kOrderCap;
+    // 4. placement: the slot order in LDS (cells known from step 1), or direct writes
     bool bad = false;
-    for (int k0 = a + tid; k0 < e; k0 += kSegUnroll * kSegBlock) {
+    if (through_lds) {
+        for (int idx = tid; idx < P; idx += kSegBlock) {
+            const int local = atomicAdd(&cnt[pad_idx(lcell[idx])], 1);
+            if ((unsigned)local >= (unsigned)P) bad = true;
+            else order[local] = (unsigned short)idx;
+        }
+    }
+    for (int k0 = a + tid; k0 < e && !through_lds; k0 += kSegUnroll * kSegBlock) {
         float4 v[kSegUnroll];
 #pragma unroll
         for (int q = 0; q < kSegUnroll; ++q)
@@ -482,17 +494,13 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
                 bad = true;
                 continue;
             }
-            if (through_lds) {
-                order[local] = (unsigned short)(k - a);
-            } else {
-                const int dst = a + local;
-                const int i = __float_as_int(v[q].w);
-                p.sorted[dst] = make_float4(v[q].x, v[q].y, v[q].z, 0.0f);
-                p.perm[dst] = make_int2(i, i);
-                p.parent[dst] = dst;
-                p.gsize[dst] = 1;
-                p.kmap[dst] = p.stage2_k[k];
-            }
+            const int dst = a + local;
+            const int i = __float_as_int(v[q].w);
+            p.sorted[dst] = make_float4(v[q].x, v[q].y, v[q].z, 0.0f);
+            p.perm[dst] = make_int2(i, i);
+            p.parent[dst] = dst;
+            p.gsize[dst] = 1;
+            p.kmap[dst] = p.stage2_k[k];
         }
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&p.counters->error, 2u);

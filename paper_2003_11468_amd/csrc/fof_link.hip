@@ -524,8 +524,9 @@ struct BoxRegs {
 // The slow path of one staged candidate kk for the lanes in `cand`: an FP32
 // result below lo32 links; one inside the band is re-decided in double from
 // the original coordinates; a link merges the groups unless the cached roots
-// already agree.
-template <bool kFP64, bool kStats>
+// already agree. kDom: domain mode, where a link across slabs goes to the
+// boundary list (an instance of its own keeps the plain one's registers).
+template <bool kFP64, bool kStats, bool kDom>
 __device__ __forceinline__ void dense_hit(const Plan &p, const BoxRegs &br, const typename Stage<kFP64>::T &st,
                                           int kk, int jb, bool cand, float r, float4 pi, int &root_i,
                                           unsigned long long &links, unsigned long long &band, unsigned &retries)
@@ -546,7 +547,7 @@ __device__ __forceinline__ void dense_hit(const Plan &p, const BoxRegs &br, cons
         if constexpr (kFP64) rj = st.root[kk];
         else rj = __float_as_int(st.v[kk].w);
         if (rj != root_i) {
-            if (p.domains > 1 && domain_of(p, j) != slab_of(pi.x, p.domains, br.L))
+            if (kDom && domain_of(p, j) != slab_of(pi.x, p.domains, br.L))
                 defer_boundary(p, root_i, rj, retries);
             else root_i = unite_root(p.parent, root_i, rj, retries);
         }
@@ -576,7 +577,7 @@ __device__ __forceinline__ bool link_f64_staged(const StageD &st, int kk, double
 
 // Tests the staged candidates [0, cnt) against the wave's home particles.
 // kSelf: the candidates come from the home cell; only j > i counts.
-template <bool kFP64, bool kStats, bool kSelf>
+template <bool kFP64, bool kStats, bool kDom, bool kSelf>
 __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, const typename Stage<kFP64>::T &st,
                                             int cnt, int jb, int i, bool vi, float4 pi, float hx, float hy,
                                             float hz, double dxi, double dyi, double dzi, double Lx, double Ly,
@@ -599,10 +600,10 @@ __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, co
                 c3 = c3 && kk + 3 > rel;
             }
             if (__ballot(c0 || c1 || c2 || c3)) {
-                dense_hit<kFP64, kStats>(p, br, st, kk + 0, jb, c0, r0, pi, root_i, links, band, retries);
-                dense_hit<kFP64, kStats>(p, br, st, kk + 1, jb, c1, r1, pi, root_i, links, band, retries);
-                dense_hit<kFP64, kStats>(p, br, st, kk + 2, jb, c2, r2, pi, root_i, links, band, retries);
-                dense_hit<kFP64, kStats>(p, br, st, kk + 3, jb, c3, r3, pi, root_i, links, band, retries);
+                dense_hit<kFP64, kStats, kDom>(p, br, st, kk + 0, jb, c0, r0, pi, root_i, links, band, retries);
+                dense_hit<kFP64, kStats, kDom>(p, br, st, kk + 1, jb, c1, r1, pi, root_i, links, band, retries);
+                dense_hit<kFP64, kStats, kDom>(p, br, st, kk + 2, jb, c2, r2, pi, root_i, links, band, retries);
+                dense_hit<kFP64, kStats, kDom>(p, br, st, kk + 3, jb, c3, r3, pi, root_i, links, band, retries);
             }
         }
     }
@@ -616,11 +617,11 @@ __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, co
             c = r <= br.hi32;   // false for invalid (NaN) lanes and candidates
         }
         if constexpr (kSelf) c = c && kk > rel;
-        if (__ballot(c)) dense_hit<kFP64, kStats>(p, br, st, kk, jb, c, r, pi, root_i, links, band, retries);
+        if (__ballot(c)) dense_hit<kFP64, kStats, kDom>(p, br, st, kk, jb, c, r, pi, root_i, links, band, retries);
     }
 }
 
-template <bool kFP64, bool kStats>
+template <bool kFP64, bool kStats, bool kDom>
 __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
 {
     using StageT = typename Stage<kFP64>::T;
@@ -693,10 +694,10 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
                 const int cnt = min(64, j1 - jb);
                 if (kStats) tests += (unsigned long long)cnt * (unsigned long long)n_home;
                 if (self)
-                    dense_batch<kFP64, kStats, true>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi, dzi, Lx,
+                    dense_batch<kFP64, kStats, kDom, true>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi, dzi, Lx,
                                                      Ly, Lz, root_i, links, band, retries);
                 else
-                    dense_batch<kFP64, kStats, false>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi, dzi,
+                    dense_batch<kFP64, kStats, kDom, false>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi, dzi,
                                                       Lx, Ly, Lz, root_i, links, band, retries);
                 __builtin_amdgcn_wave_barrier();
             }
@@ -861,7 +862,12 @@ void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
     // the sub-cell pre-merge would merge across slab faces: not in domain mode
     if (p.domains <= 1)
         hipLaunchKernelGGL(k_dense_premerge, dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
-    hipLaunchKernelGGL((k_link_dense<kFP64, kStats>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
+    if (p.domains > 1)
+        hipLaunchKernelGGL((k_link_dense<kFP64, kStats, true>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0,
+                           stream, p);
+    else
+        hipLaunchKernelGGL((k_link_dense<kFP64, kStats, false>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0,
+                           stream, p);
     if (t) t->mark(K_LINK_DENSE, true, stream);
     if (p.domains > 1) {
         // global merge, timed with the union pass
