@@ -89,7 +89,12 @@ typedef struct {
                                 inside each slab, links across slabs are collected, their groups are
                                 numbered densely and merged by a second union-find, and the roots are
                                 updated. Same labels as without; at most 4096. 0 or 1 = off */
-    int32_t reserved[3];     /* must be zero */
+    int32_t link_order;      /* which root a merge hooks under the other (paper, Section 3.2):
+                                0 = by index, the larger under the smaller (default);
+                                1 = randomised linking: by a fixed pseudo-random priority of the index
+                                (a bijection), a contention variant. Same labels either way: the label
+                                is the smallest original index of the group, whatever its root */
+    int32_t reserved[2];     /* must be zero */
 } fof_options;
 
 typedef struct {
@@ -106,7 +111,10 @@ typedef struct {
     int64_t dense_items;     /* wavefront work items (64 particles of a dense cell each) */
     int64_t boundary_links;  /* domain mode: linked pairs across slabs (the exchanged link list) */
     int64_t boundary_groups; /* domain mode: distinct slab-local groups in that list */
-    int64_t reserved[3];
+    int64_t find_depth_max;  /* longest path to a root when linking ends (collect_stats only) */
+    int64_t find_depth_sum;  /* sum over particles of their path length to the root (collect_stats
+                                only; mean depth = find_depth_sum / n_particles) */
+    int64_t reserved[1];
 } fof_stats;
 
 /* Geometry and FP32 decision thresholds the library uses for one box. */

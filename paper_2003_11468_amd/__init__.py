@@ -26,6 +26,7 @@ FOF_OK, FOF_ERR_INVALID_ARG, FOF_ERR_OUT_OF_BOX, FOF_ERR_BAD_STATE, FOF_ERR_WORK
     FOF_ERR_UNSUPPORTED = range(7)
 FOF_PRED_FP64, FOF_PRED_FP32_FILTER = 0, 1
 PREDICATES = {"fp64": FOF_PRED_FP64, "fp32_filter": FOF_PRED_FP32_FILTER}
+LINK_ORDERS = {"index": 0, "random": 1}   # fof_options.link_order
 
 
 class FoFError(RuntimeError):
@@ -39,7 +40,7 @@ class Options(ctypes.Structure):
     _fields_ = [("predicate", ctypes.c_int32), ("strict_less", ctypes.c_int32), ("cell_factor", ctypes.c_double),
                 ("collect_stats", ctypes.c_int32), ("dense_min", ctypes.c_int32), ("collect_timings", ctypes.c_int32),
                 ("sort_segment_log2", ctypes.c_int32), ("domains", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("link_order", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -48,7 +49,8 @@ class Stats(ctypes.Structure):
                 ("cas_retries", ctypes.c_int64), ("fp64_boxes", ctypes.c_int64),
                 ("sparse_pair_tests", ctypes.c_int64), ("queued_links", ctypes.c_int64),
                 ("dense_items", ctypes.c_int64), ("boundary_links", ctypes.c_int64),
-                ("boundary_groups", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
+                ("boundary_groups", ctypes.c_int64), ("find_depth_max", ctypes.c_int64),
+                ("find_depth_sum", ctypes.c_int64), ("reserved", ctypes.c_int64 * 1)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -264,10 +266,11 @@ def fof_status_string(status: int) -> str:
 
 def make_options(predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
                  stats: bool = False, dense_min: int = 0, timings: bool = False, segment_log2: int = 0,
-                 domains: int = 0) -> Options:
+                 domains: int = 0, link_order: str = "index") -> Options:
     o = fof_default_options()
     o.sort_segment_log2 = int(segment_log2)
     o.domains = int(domains)
+    o.link_order = LINK_ORDERS[link_order]
     o.collect_timings = int(timings)
     o.predicate = PREDICATES[predicate]
     o.strict_less = int(strict)
@@ -282,13 +285,13 @@ class FoF:
 
     def __init__(self, predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
                  stats: bool = False, stream=None, dense_min: int = 0, timings: bool = False,
-                 segment_log2: int = 0, domains: int = 0):
+                 segment_log2: int = 0, domains: int = 0, link_order: str = "index"):
         import torch
 
         self._torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats, dense_min, timings, segment_log2,
-                                           domains), self.stream.cuda_stream)
+                                           domains, link_order), self.stream.cuda_stream)
         self.ws = None
 
     def close(self):

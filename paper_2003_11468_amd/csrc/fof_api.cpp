@@ -149,7 +149,8 @@ bool options_valid(const fof_options &o)
     if (o.sort_segment_log2 != 0 && (o.sort_segment_log2 < fof::kSegLog2Min || o.sort_segment_log2 > fof::kSegLog2Max))
         return false;
     if (o.domains < 0 || o.domains > kMaxDomains) return false;
-    for (int k = 0; k < 3; ++k)
+    if (o.link_order != 0 && o.link_order != 1) return false;
+    for (int k = 0; k < 2; ++k)
         if (o.reserved[k] != 0) return false;
     return true;
 }
@@ -402,6 +403,7 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.dense_blocks = kDenseBlocks;
     d.sparse_blocks = kSparseBlocks;
     d.domains = c->opt.domains > 1 ? c->opt.domains : 0;
+    d.link_random = c->opt.link_order == 1 ? 1 : 0;
     d.max_items = p.max_items;
     d.max_edges = p.max_edges;
     d.box0 = p.boxes[0];
@@ -646,6 +648,8 @@ fof_status fof_get_stats(fof_ctx *ctx, fof_stats *out)
     out->dense_items = (int64_t)cnt.n_items;
     out->boundary_links = (int64_t)cnt.n_boundary;
     out->boundary_groups = (int64_t)cnt.n_bgroups;
+    out->find_depth_max = (int64_t)cnt.depth_max;
+    out->find_depth_sum = (int64_t)cnt.depth_sum;
     return st;
 }
 

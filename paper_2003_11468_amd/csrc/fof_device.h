@@ -88,7 +88,7 @@ __device__ __forceinline__ void st_rel(int *a, int v)
 
 // Root of x with path halving: each visited node is re-pointed to its
 // grandparent. The store may race with other finds; every value written is an
-// ancestor of the node with a smaller index, so the forest stays valid.
+// ancestor of the node, so the forest stays valid.
 __device__ __forceinline__ int find_halve(int *parent, int x)
 {
     while (true) {
@@ -101,18 +101,36 @@ __device__ __forceinline__ int find_halve(int *parent, int x)
     }
 }
 
-// Merge the groups of a and b: hook the larger root under the smaller with a
-// compare-and-swap that expects the larger root to still be a root. On failure
-// the CAS returns the node's new parent, and the search continues from there.
-__device__ __forceinline__ unsigned unite(int *parent, int a, int b)
+// Hooking priority of node x (paper, Section 3.2): the index itself, or, for
+// randomised linking, a fixed pseudo-random bijection of it (the 32-bit
+// finaliser of MurmurHash3: xor-shifts and odd multipliers, each invertible
+// modulo 2^32). A strict total order either way, so two roots never tie.
+__device__ __forceinline__ unsigned link_key(int x, bool random)
+{
+    unsigned h = (unsigned)x;
+    if (random) {
+        h ^= h >> 16;
+        h *= 0x85ebca6bu;
+        h ^= h >> 13;
+        h *= 0xc2b2ae35u;
+        h ^= h >> 16;
+    }
+    return h;
+}
+
+// Merge the groups of a and b: hook the root of lower priority under the other
+// with a compare-and-swap that expects it to still be a root. On failure the
+// CAS returns the node's new parent, and the search continues from there.
+__device__ __forceinline__ unsigned unite(int *parent, int a, int b, bool random)
 {
     unsigned retries = 0;
     while (true) {
         a = find_halve(parent, a);
         b = find_halve(parent, b);
         if (a == b) return retries;
-        int lo = a < b ? a : b;
-        int hi = a < b ? b : a;
+        const bool a_first = link_key(a, random) < link_key(b, random);
+        int lo = a_first ? a : b;
+        int hi = a_first ? b : a;
         int expected = hi;
         if (__hip_atomic_compare_exchange_strong(parent + hi, &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT))

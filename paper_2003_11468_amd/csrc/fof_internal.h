@@ -38,7 +38,8 @@ struct Counters {
     unsigned int n_edges;       // linked pairs queued for the union kernel (summed after the search)
     unsigned int n_boundary;    // domain mode: linked pairs across domains (may exceed the list's capacity)
     unsigned int n_bgroups;     // domain mode: distinct local groups met by those pairs
-    unsigned int pad[3];
+    unsigned int depth_max;     // stats: longest path to a root before the flatten
+    unsigned long long depth_sum;   // stats: sum of those path lengths
 };
 
 // Everything a launch needs: raw pointers into the caller's workspace.
@@ -60,7 +61,7 @@ struct Plan {
     int32_t dense_blocks;   // grid of the persistent dense link kernel
     int32_t sparse_blocks;  // grid of the persistent sparse link kernel
     int32_t domains;        // > 1: slabs along x, local union-find per slab, then a global merge
-    int32_t pad1;
+    int32_t link_random;    // 1: roots hook by a pseudo-random priority of the index, not the index
     int64_t max_items;      // capacity of `items`
     int64_t max_edges;      // capacity of `edges`: kEdgeSlices slices of max_edges / kEdgeSlices
 

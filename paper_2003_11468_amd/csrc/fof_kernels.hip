@@ -68,6 +68,8 @@ __global__ void __launch_bounds__(kBlock) k_clear(Plan p)
         p.counters->n_edges = 0;
         p.counters->n_boundary = 0;
         p.counters->n_bgroups = 0;
+        p.counters->depth_max = 0;
+        p.counters->depth_sum = 0;
     }
 }
 
@@ -530,6 +532,31 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     }
 }
 
+// Statistics only, before the flatten: the length of every particle's path
+// to its root (the find depth that the cost of linking depends on, paper,
+// Section 4), as a maximum and a sum.
+__global__ void __launch_bounds__(kBlock) k_find_depth(Plan p)
+{
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < p.n; base += (int64_t)gridDim.x * kBlock) {
+        const int64_t s64 = base + threadIdx.x;
+        unsigned d = 0;
+        if (s64 < p.n) {
+            int r = (int)s64;
+            for (int q = p.parent[r]; q != r; q = p.parent[r]) {
+                r = q;
+                ++d;
+            }
+        }
+        unsigned dm = d;
+        for (int k = 32; k >= 1; k >>= 1) dm = max(dm, (unsigned)__shfl_xor((int)dm, k, 64));
+        const unsigned long long ds = wave_sum_u64(d);
+        if (lane_id() == 0) {
+            atomicMax(&p.counters->depth_max, dm);
+            atomicAdd(&p.counters->depth_sum, ds);
+        }
+    }
+}
+
 // Consecutive sorted particles often share their root, so the root updates of
 // runs of equal roots in a wave are combined before the atomics.
 __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
@@ -674,6 +701,8 @@ __global__ void __launch_bounds__(kBlock) k_relink_reset(Plan p)
         p.counters->n_edges = 0;
         p.counters->n_boundary = 0;
         p.counters->n_bgroups = 0;
+        p.counters->depth_max = 0;
+        p.counters->depth_sum = 0;
     }
 }
 
@@ -845,6 +874,7 @@ hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
     if (p.n == 0) return hipSuccess;
     const unsigned flatten_grid = (unsigned)min(kStreamBlocks, grid_tiles(p.n));
+    if (p.stats) hipLaunchKernelGGL(k_find_depth, dim3(flatten_grid), dim3(kBlock), 0, stream, p);
     FOF_TIMED(K_FLATTEN, hipLaunchKernelGGL(k_flatten, dim3(flatten_grid), dim3(kBlock), 0, stream, p));
     FOF_TIMED(K_RESOLVE, {
         hipLaunchKernelGGL(k_resolve, dim3(xcd_grid(grid_tiles(p.n))), dim3(kBlock), 0, stream, p);

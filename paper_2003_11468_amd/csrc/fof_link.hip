@@ -42,15 +42,16 @@ constexpr int kWaves = kBlock / 64;
 __device__ __forceinline__ float qnan() { return __builtin_nanf(""); }
 
 // Merge the groups that contain roots-or-members a and b; returns a node of the
-// merged group (the smaller root at the time of the merge).
-__device__ __forceinline__ int unite_root(int *parent, int a, int b, unsigned &retries)
+// merged group (the root that stayed a root at the time of the merge).
+__device__ __forceinline__ int unite_root(int *parent, int a, int b, bool random, unsigned &retries)
 {
     while (true) {
         a = find_halve(parent, a);
         b = find_halve(parent, b);
         if (a == b) return a;
-        const int lo = a < b ? a : b;
-        const int hi = a < b ? b : a;
+        const bool a_first = link_key(a, random) < link_key(b, random);
+        const int lo = a_first ? a : b;
+        const int hi = a_first ? b : a;
         int expected = hi;
         if (__hip_atomic_compare_exchange_strong(parent + hi, &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT))
@@ -89,7 +90,7 @@ __device__ __forceinline__ void defer_boundary(const Plan &p, int a, int b, unsi
 {
     const unsigned at = atomicAdd(&p.counters->n_boundary, 1u);
     if ((int64_t)at < p.max_edges) p.bnd[at] = make_int2(a, b);
-    else retries += unite(p.parent, a, b);
+    else retries += unite(p.parent, a, b, p.link_random);
 }
 
 // Merge of a linked pair found by the search: at once, or in domain mode
@@ -97,7 +98,7 @@ __device__ __forceinline__ void defer_boundary(const Plan &p, int a, int b, unsi
 __device__ __forceinline__ void merge_pair(const Plan &p, int a, int b, unsigned &retries)
 {
     if (p.domains > 1 && domain_of(p, a) != domain_of(p, b)) defer_boundary(p, a, b, retries);
-    else retries += unite(p.parent, a, b);
+    else retries += unite(p.parent, a, b, p.link_random);
 }
 
 // --------------------------------------------------------- sparse (lane) --
@@ -549,7 +550,7 @@ __device__ __forceinline__ void dense_hit(const Plan &p, const BoxRegs &br, cons
         if (rj != root_i) {
             if (kDom && domain_of(p, j) != slab_of(pi.x, p.domains, br.L))
                 defer_boundary(p, root_i, rj, retries);
-            else root_i = unite_root(p.parent, root_i, rj, retries);
+            else root_i = unite_root(p.parent, root_i, rj, p.link_random, retries);
         }
     }
 }
@@ -762,7 +763,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
         __builtin_amdgcn_wave_barrier();
         for (int j = cs + lane; j < ce; j += 64) {
             const int r = rp[sub_of(j)];
-            if (r != j) retries += unite(p.parent, j, r);
+            if (r != j) retries += unite(p.parent, j, r, p.link_random);
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -831,7 +832,7 @@ __global__ void __launch_bounds__(kBlock) k_gm_union(Plan p)
     const int64_t nb = gm_pairs(p);
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nb; k += (int64_t)gridDim.x * kBlock) {
         const int2 e = p.bnd[k];
-        (void)unite(gp, num[e.x], num[e.y]);
+        (void)unite(gp, num[e.x], num[e.y], false);
     }
 }
 

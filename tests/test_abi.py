@@ -50,9 +50,18 @@ def test_create_rejects_bad_options():
     with pytest.raises(fof.FoFError):
         fof.fof_create(o)
     o = fof.fof_default_options()
-    o.reserved[2] = 1
+    o.reserved[1] = 1
     with pytest.raises(fof.FoFError):
         fof.fof_create(o)
+    for bad in (-1, 2):
+        o = fof.fof_default_options()
+        o.link_order = bad
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_create(o)
+        assert e.value.status == fof.FOF_ERR_INVALID_ARG
+    o = fof.fof_default_options()
+    o.link_order = 1
+    fof.fof_destroy(fof.fof_create(o))
 
 
 def test_workspace_bytes_scales_with_particles_and_cells():

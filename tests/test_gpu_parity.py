@@ -21,9 +21,9 @@ PREDICATES = ["fp32_filter", "fp64"]
 
 
 def gpu_run(pos, offsets, box, lx, predicate="fp32_filter", strict=False, cell_factor=0.0, stats=False,
-            dense_min=0, segment_log2=0, domains=0):
+            dense_min=0, segment_log2=0, domains=0, link_order="index"):
     f = fof.FoF(predicate, strict, cell_factor, stats, dense_min=dense_min, segment_log2=segment_log2,
-                domains=domains)
+                domains=domains, link_order=link_order)
     try:
         p = torch.from_numpy(np.ascontiguousarray(pos, dtype=np.float32)).cuda()
         label, size, ng = f.run(p, offsets, box, lx)
@@ -278,6 +278,53 @@ def test_domain_decomposed_merge(domains):
     for predicate in PREDICATES:
         lab, size, ng, _ = gpu_run(w.pos, w.offsets, w.box, w.lx, predicate, dense_min=16, domains=domains)
         assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and np.array_equal(ng, ref[2])
+
+
+# Randomised linking (Section 3.2): roots hook by a fixed pseudo-random
+# priority of the index instead of the index. Which node ends up a root
+# changes; the labels (smallest original index of each group), the sizes and
+# the group counts must not. Every kernel path, both predicates, domain mode,
+# one lattice-wide group (the most contended case) and batches.
+def test_randomised_linking_same_labels():
+    n = 150000
+    pos = synth.clustered(n, 53, 0, 0.7)
+    for b, cf, dm in ((0.2, 2.0, 32), (0.5, 1.0, 8), (0.9, 0.0, 4)):
+        lx = synth.linking_length(b, n)
+        ref = oracle.fof(pos, lx)
+        for predicate in PREDICATES:
+            for domains in (0, 3):
+                lab, size, ng, st = gpu_run(pos, [0, n], 1.0, lx, predicate, cell_factor=cf, dense_min=dm,
+                                            stats=True, domains=domains, link_order="random")
+                assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and int(ng[0]) == ref[2]
+                assert st["links"] >= n - ref[2]
+    fx = load_fixture("fig2_indirect_u.txt")
+    lab, size, _, _ = gpu_run(fx["pos"], [0, len(fx["pos"])], fx["box"], fx["lx"], link_order="random")
+    assert np.array_equal(lab, fx["labels_le"]) and np.array_equal(size, fx["sizes_le"])
+    pos = lattice(40, seed=5)
+    for dm in (1, 1 << 30):
+        lab, size, ng, _ = gpu_run(pos, [0, len(pos)], 1.0, (1 + 1e-3) / 40, dense_min=dm, link_order="random")
+        assert int(ng[0]) == 1 and np.all(lab == 0) and size[0] == 40 ** 3
+    w = synth.make("batched256", n_boxes=12, size_scale=0.05)
+    ref = oracle.fof_boxes(w.pos, w.offsets, w.box, w.lx)
+    lab, size, ng, _ = gpu_run(w.pos, w.offsets, w.box, w.lx, dense_min=16, link_order="random")
+    assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and np.array_equal(ng, ref[2])
+
+
+# Find depth statistics: every non-root is at least one step from its root,
+# a forest of singletons has depth 0, and the sum is bounded by max x n.
+def test_find_depth_statistics():
+    n = 100000
+    pos = synth.clustered(n, 57, 0, 0.6)
+    lx = synth.linking_length(0.5, n)
+    ref = oracle.fof(pos, lx)
+    for order in ("index", "random"):
+        _, _, ng, st = gpu_run(pos, [0, n], 1.0, lx, stats=True, link_order=order)
+        assert int(ng[0]) == ref[2]
+        assert st["find_depth_max"] >= 1
+        assert n - ref[2] <= st["find_depth_sum"] <= st["find_depth_max"] * n
+    pos = lattice(16, seed=3)
+    _, _, ng, st = gpu_run(pos, [0, len(pos)], 1.0, (1 - 1e-3) / 16, stats=True)
+    assert int(ng[0]) == 16 ** 3 and st["find_depth_max"] == 0 and st["find_depth_sum"] == 0
 
 
 # Relink: new linking lengths over the cells of the last build (each at most
