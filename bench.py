@@ -48,9 +48,9 @@ def algorithmic_bytes(kernel: str, n: int, cells: int, nonroot: int, edges: int)
         "k_seg_hist": 16 * n,                     # staged particle in (segment histogram stays in LDS)
         "k_seg_scan": 8 * segments,
         "k_seg_scatter": n * (16 + 16 + 4),       # staged particle in; segment-ordered particle + slot out
-        # segment-ordered particle + slot in; sorted xyz, perm, parent, size, slot map out; cell starts
-        # and occupancy bits out
-        "k_cell_sort": n * (16 + 4 + 16 + 8 + 4 + 4 + 4) + cells * 4 + cells // 8,
+        # segment-ordered particle + slot in; sorted xyz, perm, parent, size, slot map out; the starts
+        # of the occupied cells (at most one per particle) and the occupancy words (8 B per 32 cells) out
+        "k_cell_sort": n * (16 + 4 + 16 + 8 + 4 + 4 + 4) + 4 * min(n, cells) + cells // 4,
         "k_union_edges": 8 * edges,
         "k_flatten": 4 * n + nonroot * (4 + 4 + 8),  # parent in; root out, perm in, two atomics per non-root
         "k_resolve": n * (4 + 8 + 4 + 8),         # parent, perm, staging slot in; label+size per staging slot out

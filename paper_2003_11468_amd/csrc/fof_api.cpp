@@ -303,7 +303,7 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.o_p0 = take(sizeof(int64_t) * ((size_t)n_boxes + 1));
     p.o_counters = take(sizeof(Counters));
     p.o_groups = take(sizeof(unsigned long long) * (size_t)n_boxes);
-    p.o_cell = take(sizeof(int32_t) * ((size_t)cells + 1));
+    p.o_cell = take(sizeof(int32_t) * (n + 4));   // starts of the occupied cells (at most n) + sentinels
     p.o_part = take(sizeof(int32_t) * (size_t)p.scan_tiles);
     p.o_kmap = take(sizeof(int32_t) * n);
     p.o_sorted = take(sizeof(float) * 4 * n);
@@ -322,7 +322,7 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.o_staging = take(sizeof(float) * 4 * n);
     p.o_stpos = take(sizeof(int32_t) * n);
     p.o_wave_roots = take(sizeof(int32_t) * ((n + 63) / 64));
-    p.o_occ = take(sizeof(uint32_t) * (((size_t)p.n_segments << (p.seg_shift - 5)) + 2));
+    p.o_occ = take(sizeof(uint2) * (((size_t)p.n_segments << (p.seg_shift - 5)) + 2));
     p.o_seg = take(sizeof(int32_t) * (size_t)p.n_segments);
     p.o_staging2 = take(sizeof(float) * 4 * n);
     p.o_stage2_k = take(sizeof(int32_t) * n);
@@ -411,7 +411,7 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.box_p0 = at<int64_t>(c->ws, p.o_p0);
     d.counters = at<Counters>(c->ws, p.o_counters);
     d.n_groups = at<unsigned long long>(c->ws, p.o_groups);
-    d.cell = at<int32_t>(c->ws, p.o_cell);
+    d.cstart = at<int32_t>(c->ws, p.o_cell);
     d.scan_part = at<int32_t>(c->ws, p.o_part);
     d.kmap = at<int32_t>(c->ws, p.o_kmap);
     d.sorted = at<float4>(c->ws, p.o_sorted);
@@ -425,7 +425,7 @@ fof_status install_plan(fof_ctx *c, HostPlan &&np)
     d.staging = at<float4>(c->ws, p.o_staging);
     d.stpos = at<int32_t>(c->ws, p.o_stpos);
     d.wave_roots = at<int32_t>(c->ws, p.o_wave_roots);
-    d.occ = at<uint32_t>(c->ws, p.o_occ);
+    d.occ = at<uint2>(c->ws, p.o_occ);
     d.seg_end = at<int32_t>(c->ws, p.o_seg);
     d.staging2 = at<float4>(c->ws, p.o_staging2);
     d.stage2_k = at<int32_t>(c->ws, p.o_stage2_k);

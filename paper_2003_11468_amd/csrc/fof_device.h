@@ -141,6 +141,18 @@ __device__ __forceinline__ unsigned unite(int *parent, int a, int b, bool random
     }
 }
 
+// ------------------------------------------------------------ cell index --
+// Sorted slots [x, y) of cell c: its occupancy word gives the rank of the cell
+// among the occupied cells, and cstart the slot of that rank (an empty cell
+// gives an empty range).
+__device__ __forceinline__ int2 cell_span(const Plan &p, int c)
+{
+    const uint2 w = p.occ[c >> 5];
+    const int r = (int)w.y + __popc(w.x & ((1u << (c & 31)) - 1u));
+    const int s = p.cstart[r];
+    return make_int2(s, ((w.x >> (c & 31)) & 1u) ? p.cstart[r + 1] : s);
+}
+
 // ------------------------------------------------------------ wave utils --
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)

@@ -70,7 +70,8 @@ struct Plan {
     const BoxDev *boxes;    // [n_boxes] (read only when n_boxes > 1)
     const int64_t *box_p0;  // [n_boxes + 1] particle offsets
 
-    int32_t *cell;          // [n_cells + 1] first sorted slot of each cell; cell[n_cells] = n
+    int32_t *cstart;        // [n + 4] first sorted slot of each occupied cell, by rank (see occ);
+                            // entries n .. n + 3 hold n
     int32_t *seg_end;       // [n_segments] counts, exclusive prefix, then (after the segment pass) end slots
     int32_t *scan_part;     // [scan_tiles] tile sums of every scan level
     int32_t *bucket_hist;   // [n_buckets * n_tiles + 1] counts, then output offsets (bucket-major);
@@ -79,7 +80,10 @@ struct Plan {
     int32_t *stpos;         // [n] staging slot of input particle i
     float4 *staging2;       // [n] segment order (cells of a segment together, unordered inside)
     int32_t *stage2_k;      // [n] staging slot of each segment-order slot
-    uint32_t *occ;          // [n_segments << (seg_shift - 5) + 2] bit c: cell c holds a particle
+    uint2 *occ;             // [n_segments << (seg_shift - 5) + 2] per 32 cells: .x bit k: cell 32w + k
+                            // holds a particle; .y the cstart index of the first occupied cell at or
+                            // after cell 32w. Cell c starts at sorted slot
+                            // cstart[occ[c/32].y + (occupied cells of that word below c)]
     int32_t *wave_roots;    // [n_waves] roots among the 64 sorted slots of each wave (resolve)
     int64_t n_waves;
     int32_t *kmap;          // [n] staging slot of each sorted slot

@@ -376,9 +376,15 @@ __device__ __forceinline__ int pad_idx(int c) { return c + (c >> 5); }
 //  1. count the cells in LDS;
 //  2. exclusive prefix: thread t owns a run of consecutive cells (one block
 //     scan, no per-step wave scans);
-//  3. cell starts, occupancy bits (one 64-bit word per wave step) and dense
-//     link work items {cell, first home particle, box, 0}, one per 64
-//     particles of every cell with at least dense_min particles;
+//  3. occupancy words, the starts of the occupied cells and dense link work
+//     items {cell, first home particle, box, 0}, one per 64 particles of
+//     every cell with at least dense_min particles. The k-th occupied cell
+//     of the segment (in cell order) stores its first slot at cstart[a + k]:
+//     a segment has at most P occupied cells, so segments never overlap, and
+//     no array is sized by the cell count except the occupancy words. The
+//     entry after the last occupied cell of a segment holds e: written here
+//     when the segment has fewer occupied cells than particles, else it is
+//     the next segment's first entry (or the final sentinel), which is e too;
 //  4. place the particles: the LDS cursors give each its slot; up to
 //     kOrderCap particles the slot order is kept in LDS and the outputs are
 //     written in slot order (coalesced), otherwise written directly.
@@ -392,6 +398,7 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     __shared__ int cnt[(1 << kLog2) + (1 << (kLog2 - 5)) + 1];
     __shared__ unsigned short order[kOrderCap];
     __shared__ unsigned short lcell[kOrderCap];   // cell (in the segment) of each particle, when P <= kOrderCap
+    __shared__ int gocc[(1 << kLog2) >> 6];        // occupied cells per 64-cell group, then their prefix
     __shared__ int lds[kSegWaves];
     const int j = (int)blockIdx.x;
     const int seg_cells = 1 << p.seg_shift;
@@ -442,18 +449,37 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     }
     __syncthreads();
 
-    // 3. cell starts, occupancy bits, dense work items (64 consecutive cells per wave step)
+    // 3. occupancy words, starts of the occupied cells, dense work items (64
+    //    consecutive cells per wave step, so lane 0 of a step owns two words)
     {
         const int lane = lane_id();
-        const int64_t n_cells = p.n_cells;
+        const int groups = seg_cells >> 6;
+        for (int c = tid; c < seg_cells; c += kSegBlock) {
+            const unsigned long long bits = __ballot(cnt[pad_idx(c + 1)] != cnt[pad_idx(c)]);
+            if (lane == 0) gocc[c >> 6] = __popcll(bits);
+        }
+        __syncthreads();
+        {
+            const int v = tid < groups ? gocc[tid] : 0;   // at most 256 groups
+            int n_occ;
+            const int run = block_excl_scan<kSegBlock>(v, lds, &n_occ);
+            if (tid < groups) gocc[tid] = run;
+            if (tid == 0 && n_occ < P) p.cstart[a + n_occ] = e;
+        }
+        __syncthreads();
         for (int c = tid; c < seg_cells; c += kSegBlock) {
             const int st = cnt[pad_idx(c)];
             const int v = cnt[pad_idx(c + 1)] - st;
             const int start = a + st;
             const int gc = cell0 + c;
-            if (gc <= n_cells) p.cell[gc] = start;          // cell n_cells (the end) has no particle: start = n
             const unsigned long long bits = __ballot(v > 0);
-            if (lane == 0) *reinterpret_cast<unsigned long long *>(p.occ + ((cell0 + c) >> 5)) = bits;
+            const int base = a + gocc[c >> 6];
+            if (v > 0) p.cstart[base + __popcll(bits & ((1ull << lane) - 1ull))] = start;
+            if (lane == 0) {
+                const unsigned lo = (unsigned)bits, hi = (unsigned)(bits >> 32);
+                *reinterpret_cast<uint4 *>(p.occ + (gc >> 5)) =
+                    make_uint4(lo, (unsigned)base, hi, (unsigned)(base + __popc(lo)));
+            }
             const int chunks = (v >= p.dense_min && v > 0) ? (v + 63) >> 6 : 0;
             if (__ballot(chunks > 0)) {
                 const int cincl = wave_incl_scan(chunks);
@@ -468,8 +494,13 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
                 }
             }
         }
-        // the end marker when the cells fill the last segment exactly
-        if (j + 1 == (int)gridDim.x && tid == 0 && (n_cells & (seg_cells - 1)) == 0) p.cell[n_cells] = e;
+        // the final sentinel (the end of the last occupied cell, and the
+        // padding of 16-byte reads) and the two occupancy words after the last
+        // segment (the end of the last cell when the cells fill it exactly)
+        if (j + 1 == (int)gridDim.x && tid < 4) {
+            p.cstart[p.n + tid] = (int)p.n;
+            if (tid < 2) p.occ[((int64_t)gridDim.x << (p.seg_shift - 5)) + tid] = make_uint2(0u, (unsigned)p.n);
+        }
     }
     __syncthreads();
 

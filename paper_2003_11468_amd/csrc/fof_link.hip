@@ -353,23 +353,33 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
             const int cz = cell_coord(pi.z, bd.inv_h, nc);
             const int cb = (int)bd.cell_base;
             const int c = cb + (cz * nc + cy) * nc + cx;
-            const int *cell = p.cell;
+            const int *cst = p.cstart;
             const int dense_min = p.dense_min;
+            const int seg_shift = p.seg_shift;
             const int rb0 = c - cx;
             // Boundaries of the own row and the four neighbour rows (dy, dz) =
             // (1, 0), (-1, 1), (0, 1), (1, 1): with the own cell these hold the
             // 13 half-shell cells. All are requested before any is used.
-            // Occupancy bits first (one bit per cell, a small array that stays
-            // in cache): boundaries are read only for rows with a particle.
-            const uint32_t *occ = p.occ;
-            auto occupied = [&](int cell_index) { return (occ[cell_index >> 5] >> (cell_index & 31)) & 1u; };
-            const int own_start = cell[c], own_end = cell[c + 1];
+            // Occupancy words first (bits and rank base per 32 cells, a small
+            // array that stays in cache): boundaries are read only for rows
+            // with a particle, from the starts of the occupied cells.
+            const uint2 *occ = p.occ;
+            auto rank_in = [](uint2 w, int cell_index) {
+                return (int)w.y + __popc(w.x & ((1u << (cell_index & 31)) - 1u));
+            };
+            auto span = [&](int cell_index, int &s0, int &s1) {   // left at 0, 0 for an empty cell
+                const uint2 w = occ[cell_index >> 5];
+                if ((w.x >> (cell_index & 31)) & 1u) {
+                    const int r = rank_in(w, cell_index);
+                    s0 = cst[r];
+                    s1 = cst[r + 1];
+                }
+            };
+            const int r_own = rank_in(occ[c >> 5], c);   // the own cell holds s
+            const int own_start = cst[r_own], own_end = cst[r_own + 1];
             const int nxp = cx + 1 < nc ? cx + 1 : 0;
             int nxt_start = 0, nxt_end = 0;
-            if (occupied(rb0 + nxp)) {
-                nxt_start = cell[rb0 + nxp];
-                nxt_end = cell[rb0 + nxp + 1];
-            }
+            span(rb0 + nxp, nxt_start, nxt_end);
             const bool inner = cx >= 1 && cx + 1 < nc;
             const int rdy[4] = {1, -1, 0, 1}, rdz[4] = {0, 1, 1, 1};
             int st[4][3], en[4][3], yz[4];
@@ -385,23 +395,29 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
                 for (int e = 0; e < 3; ++e) st[r][e] = en[r][e] = 0;
                 if (inner) {
                     const int c0 = rb + cx - 1;
-                    const uint64_t w = (uint64_t)occ[c0 >> 5] | ((uint64_t)occ[(c0 >> 5) + 1] << 32);
-                    if ((w >> (c0 & 31)) & 7u) {
+                    const uint2 w0 = occ[c0 >> 5], w1 = occ[(c0 >> 5) + 1];
+                    const unsigned m = (unsigned)(((uint64_t)w0.x | ((uint64_t)w1.x << 32)) >> (c0 & 31)) & 7u;
+                    if (m && ((c0 ^ (c0 + 2)) >> seg_shift) == 0) {
+                        // the three cells in one segment: their occupied cells have
+                        // consecutive entries, so one 16-byte read holds every boundary
                         typedef int int4a4 __attribute__((ext_vector_type(4), aligned(4)));
-                        const int4a4 q = *reinterpret_cast<const int4a4 *>(cell + c0);
-                        st[r][0] = q.x; en[r][0] = q.y;
-                        st[r][1] = q.y; en[r][1] = q.z;
-                        st[r][2] = q.z; en[r][2] = q.w;
+                        const int4a4 q = *reinterpret_cast<const int4a4 *>(cst + rank_in(w0, c0));
+                        auto pick = [&](unsigned k) { return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w)); };
+                        const unsigned o1 = m & 1u, o2 = o1 + ((m >> 1) & 1u), o3 = o2 + (m >> 2);
+                        const int b1 = pick(o1), b2 = pick(o2);
+                        st[r][0] = q.x; en[r][0] = b1;
+                        st[r][1] = b1; en[r][1] = b2;
+                        st[r][2] = b2; en[r][2] = pick(o3);
+                    } else if (m) {
+#pragma unroll
+                        for (int e = 0; e < 3; ++e) span(c0 + e, st[r][e], en[r][e]);
                     }
                 } else {
 #pragma unroll
                     for (int e = 0; e < 3; ++e) {
                         int nx = cx - 1 + e;
                         nx += nx < 0 ? nc : (nx >= nc ? -nc : 0);
-                        if (occupied(rb + nx)) {
-                            st[r][e] = cell[rb + nx];
-                            en[r][e] = cell[rb + nx + 1];
-                        }
+                        span(rb + nx, st[r][e], en[r][e]);
                     }
                 }
             }
@@ -525,9 +541,10 @@ struct BoxRegs {
 // The slow path of one staged candidate kk for the lanes in `cand`: an FP32
 // result below lo32 links; one inside the band is re-decided in double from
 // the original coordinates; a link merges the groups unless the cached roots
-// already agree. kDom: domain mode, where a link across slabs goes to the
-// boundary list (an instance of its own keeps the plain one's registers).
-template <bool kFP64, bool kStats, bool kDom>
+// already agree. kGeneral: domain mode (a link across slabs goes to the
+// boundary list) and randomised linking, decided at run time; the plain
+// instance has neither, which keeps its registers and code size down.
+template <bool kFP64, bool kStats, bool kGeneral>
 __device__ __forceinline__ void dense_hit(const Plan &p, const BoxRegs &br, const typename Stage<kFP64>::T &st,
                                           int kk, int jb, bool cand, float r, float4 pi, int &root_i,
                                           unsigned long long &links, unsigned long long &band, unsigned &retries)
@@ -548,9 +565,9 @@ __device__ __forceinline__ void dense_hit(const Plan &p, const BoxRegs &br, cons
         if constexpr (kFP64) rj = st.root[kk];
         else rj = __float_as_int(st.v[kk].w);
         if (rj != root_i) {
-            if (kDom && domain_of(p, j) != slab_of(pi.x, p.domains, br.L))
+            if (kGeneral && p.domains > 1 && domain_of(p, j) != slab_of(pi.x, p.domains, br.L))
                 defer_boundary(p, root_i, rj, retries);
-            else root_i = unite_root(p.parent, root_i, rj, p.link_random, retries);
+            else root_i = unite_root(p.parent, root_i, rj, kGeneral && p.link_random, retries);
         }
     }
 }
@@ -578,7 +595,7 @@ __device__ __forceinline__ bool link_f64_staged(const StageD &st, int kk, double
 
 // Tests the staged candidates [0, cnt) against the wave's home particles.
 // kSelf: the candidates come from the home cell; only j > i counts.
-template <bool kFP64, bool kStats, bool kDom, bool kSelf>
+template <bool kFP64, bool kStats, bool kGeneral, bool kSelf>
 __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, const typename Stage<kFP64>::T &st,
                                             int cnt, int jb, int i, bool vi, float4 pi, float hx, float hy,
                                             float hz, double dxi, double dyi, double dzi, double Lx, double Ly,
@@ -601,10 +618,10 @@ __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, co
                 c3 = c3 && kk + 3 > rel;
             }
             if (__ballot(c0 || c1 || c2 || c3)) {
-                dense_hit<kFP64, kStats, kDom>(p, br, st, kk + 0, jb, c0, r0, pi, root_i, links, band, retries);
-                dense_hit<kFP64, kStats, kDom>(p, br, st, kk + 1, jb, c1, r1, pi, root_i, links, band, retries);
-                dense_hit<kFP64, kStats, kDom>(p, br, st, kk + 2, jb, c2, r2, pi, root_i, links, band, retries);
-                dense_hit<kFP64, kStats, kDom>(p, br, st, kk + 3, jb, c3, r3, pi, root_i, links, band, retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 0, jb, c0, r0, pi, root_i, links, band, retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 1, jb, c1, r1, pi, root_i, links, band, retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 2, jb, c2, r2, pi, root_i, links, band, retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 3, jb, c3, r3, pi, root_i, links, band, retries);
             }
         }
     }
@@ -618,11 +635,11 @@ __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, co
             c = r <= br.hi32;   // false for invalid (NaN) lanes and candidates
         }
         if constexpr (kSelf) c = c && kk > rel;
-        if (__ballot(c)) dense_hit<kFP64, kStats, kDom>(p, br, st, kk, jb, c, r, pi, root_i, links, band, retries);
+        if (__ballot(c)) dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk, jb, c, r, pi, root_i, links, band, retries);
     }
 }
 
-template <bool kFP64, bool kStats, bool kDom>
+template <bool kFP64, bool kStats, bool kGeneral>
 __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
 {
     using StageT = typename Stage<kFP64>::T;
@@ -650,7 +667,7 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
         const float L32 = bd.L32;
         const int local = c - cb;
         const int cx = local % nc, cy = (local / nc) % nc, cz = local / (nc * nc);
-        const int ce = __builtin_amdgcn_readfirstlane(p.cell[c + 1]);
+        const int ce = __builtin_amdgcn_readfirstlane(cell_span(p, c).y);
         const int i = first + lane;
         const bool vi = i < ce;
         const float4 pi = vi ? p.sorted[i] : make_float4(qnan(), qnan(), qnan(), 0.f);
@@ -673,8 +690,9 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
             if (nz < 0) { nz += nc; sz = L32; Lz = br.L; }
             else if (nz >= nc) { nz -= nc; hz = pi.z - L32; Lz = -br.L; }
             const int c2 = cb + (nz * nc + ny) * nc + nx;
-            int j0 = __builtin_amdgcn_readfirstlane(p.cell[c2]);
-            const int j1 = __builtin_amdgcn_readfirstlane(p.cell[c2 + 1]);
+            const int2 sp = cell_span(p, c2);
+            int j0 = __builtin_amdgcn_readfirstlane(sp.x);
+            const int j1 = __builtin_amdgcn_readfirstlane(sp.y);
             if (self) j0 = first;
             else if (!upper && j1 - j0 >= p.dense_min) continue;   // that dense cell searches this pair
 #pragma unroll 1
@@ -695,10 +713,10 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
                 const int cnt = min(64, j1 - jb);
                 if (kStats) tests += (unsigned long long)cnt * (unsigned long long)n_home;
                 if (self)
-                    dense_batch<kFP64, kStats, kDom, true>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi, dzi, Lx,
+                    dense_batch<kFP64, kStats, kGeneral, true>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi, dzi, Lx,
                                                      Ly, Lz, root_i, links, band, retries);
                 else
-                    dense_batch<kFP64, kStats, kDom, false>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi, dzi,
+                    dense_batch<kFP64, kStats, kGeneral, false>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi, dzi,
                                                       Lx, Ly, Lz, root_i, links, band, retries);
                 __builtin_amdgcn_wave_barrier();
             }
@@ -739,12 +757,13 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
         const int c = __builtin_amdgcn_readfirstlane(item.x);
         const int first = __builtin_amdgcn_readfirstlane(item.y);
         const int b = __builtin_amdgcn_readfirstlane(item.z);
-        const int cs = __builtin_amdgcn_readfirstlane(p.cell[c]);
+        const int2 sp = cell_span(p, c);
+        const int cs = __builtin_amdgcn_readfirstlane(sp.x);
         if (first != cs) continue;   // the cell's first item does the whole cell
         const BoxDev &bd = box_of(p, b);
         const int k = bd.sub_k;
         if (k == 0) continue;
-        const int ce = __builtin_amdgcn_readfirstlane(p.cell[c + 1]);
+        const int ce = __builtin_amdgcn_readfirstlane(sp.y);
         const int nc = bd.nc, local = c - (int)bd.cell_base;
         const int cx = local % nc, cy = (local / nc) % nc, cz = local / (nc * nc);
         const int nsub = k * k * k;
@@ -863,7 +882,7 @@ void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
     // the sub-cell pre-merge would merge across slab faces: not in domain mode
     if (p.domains <= 1)
         hipLaunchKernelGGL(k_dense_premerge, dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
-    if (p.domains > 1)
+    if (p.domains > 1 || p.link_random)
         hipLaunchKernelGGL((k_link_dense<kFP64, kStats, true>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0,
                            stream, p);
     else
