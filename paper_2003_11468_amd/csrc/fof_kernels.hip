@@ -367,25 +367,24 @@ constexpr int kSegWaves = kSegBlock / 64;
 constexpr int kSegUnroll = 4;            // particles in flight per thread
 constexpr int kOrderCap = 4096;          // segments up to this many particles are placed through LDS
 
-// LDS slot of cell c: one pad word per 32 cells, so a thread walking 32
-// consecutive cells and its neighbour lanes hit different banks.
-__device__ __forceinline__ int pad_idx(int c) { return c + (c >> 5); }
-
 // One work-group per segment of 2^seg_shift consecutive cells, whose P
-// particles own sorted slots [a, a + P) (seg_end).
-//  1. count the cells in LDS;
-//  2. exclusive prefix: thread t owns a run of consecutive cells (one block
-//     scan, no per-step wave scans);
-//  3. occupancy words, the starts of the occupied cells and dense link work
-//     items {cell, first home particle, box, 0}, one per 64 particles of
-//     every cell with at least dense_min particles. The k-th occupied cell
-//     of the segment (in cell order) stores its first slot at cstart[a + k]:
-//     a segment has at most P occupied cells, so segments never overlap, and
-//     no array is sized by the cell count except the occupancy words. The
-//     entry after the last occupied cell of a segment holds e: written here
-//     when the segment has fewer occupied cells than particles, else it is
-//     the next segment's first entry (or the final sentinel), which is e too;
-//  4. place the particles: the LDS cursors give each its slot; up to
+// particles own sorted slots [a, a + P) (seg_end). Its work grows with P and
+// with the segment's occupancy words (one per 32 cells), not with its cells:
+//  1. occupancy bits in LDS (an atomic OR per particle);
+//  2. rank base of every word (an exclusive prefix of the popcounts); the
+//     occupancy words {bits, a + base} go out. The k-th occupied cell of the
+//     segment (in cell order) has rank k and stores its first slot at
+//     cstart[a + k]: a segment has at most P occupied cells, so segments
+//     never overlap. The entry after the last occupied cell holds e: written
+//     here when the segment has fewer occupied cells than particles, else it
+//     is the next segment's first entry (or the final sentinel), which is e
+//     too;
+//  3. particle count per occupied cell, indexed by rank;
+//  4. exclusive prefix over the occupied cells (thread t owns a run);
+//  5. cell starts out, and dense link work items {cell, first home particle,
+//     box, 0}, one per 64 particles of every cell with at least dense_min
+//     particles (the cell of a rank is found from the rank bases);
+//  6. place the particles: the LDS cursors give each its slot; up to
 //     kOrderCap particles the slot order is kept in LDS and the outputs are
 //     written in slot order (coalesced), otherwise written directly.
 // A slot outside [0, P) cannot happen with consistent counts; it is latched
@@ -395,24 +394,27 @@ __device__ __forceinline__ int pad_idx(int c) { return c + (c >> 5); }
 template <int kLog2>
 __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
 {
-    __shared__ int cnt[(1 << kLog2) + (1 << (kLog2 - 5)) + 1];
+    constexpr int kWordsMax = (1 << kLog2) >> 5;
+    static_assert(kWordsMax <= kSegBlock, "one occupancy word per thread");
+    __shared__ int cnt[1 << kLog2];                  // per occupied cell: count, start, then cursor
+    __shared__ unsigned bits[kWordsMax];             // occupancy of the segment's cells
+    __shared__ int wbase[kWordsMax];                 // occupied cells before each word
     __shared__ unsigned short order[kOrderCap];
-    __shared__ unsigned short lcell[kOrderCap];   // cell (in the segment) of each particle, when P <= kOrderCap
-    __shared__ int gocc[(1 << kLog2) >> 6];        // occupied cells per 64-cell group, then their prefix
+    __shared__ unsigned short lrank[kOrderCap];      // per particle (P <= kOrderCap): its cell, then the cell's rank
     __shared__ int lds[kSegWaves];
+    __shared__ int occ_total;
     const int j = (int)blockIdx.x;
-    const int seg_cells = 1 << p.seg_shift;
+    const int words = 1 << (p.seg_shift - 5);
     const int cell0 = j << p.seg_shift;
     const int a = j ? p.seg_end[j - 1] : 0;
     const int e = p.seg_end[j];
     const int P = e - a;
     const int tid = (int)threadIdx.x;
-    const int sentinel = pad_idx(seg_cells);
-    for (int c = tid; c <= sentinel; c += kSegBlock) cnt[c] = 0;
+    const bool through_lds = P <= kOrderCap;
+    for (int w = tid; w < words; w += kSegBlock) bits[w] = 0u;
     __syncthreads();
 
-    // 1. counts (and, for a segment placed through LDS, each particle's cell)
-    const bool through_lds = P <= kOrderCap;
+    // 1. occupancy bits (and, for a segment placed through LDS, each particle's cell)
     for (int k0 = a + tid; k0 < e; k0 += kSegUnroll * kSegBlock) {
         float4 v[kSegUnroll];
 #pragma unroll
@@ -422,65 +424,81 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
         for (int q = 0; q < kSegUnroll; ++q)
             if (k0 + q * kSegBlock < e) {
                 const int c = staged_cell(p, v[q]) - cell0;
-                atomicAdd(&cnt[pad_idx(c)], 1);
-                if (through_lds) lcell[k0 + q * kSegBlock - a] = (unsigned short)c;
+                atomicOr(&bits[c >> 5], 1u << (c & 31));
+                if (through_lds) lrank[k0 + q * kSegBlock - a] = (unsigned short)c;
             }
     }
     __syncthreads();
 
-    // 2. exclusive prefix (local slots)
+    // 2. rank bases, occupancy words out
     {
-        const int per = seg_cells >= kSegBlock ? seg_cells / kSegBlock : 1;
-        const int c0 = tid * per;
-        const bool owns = c0 < seg_cells;
+        const unsigned b = tid < words ? bits[tid] : 0u;
+        int n_occ;
+        const int run = block_excl_scan<kSegBlock>(__popc(b), lds, &n_occ);
+        if (tid < words) {
+            wbase[tid] = run;
+            p.occ[(cell0 >> 5) + tid] = make_uint2(b, (unsigned)(a + run));
+        }
+        if (tid == 0) {
+            occ_total = n_occ;
+            if (n_occ < P) p.cstart[a + n_occ] = e;
+        }
+        for (int k = tid; k < n_occ; k += kSegBlock) cnt[k] = 0;
+    }
+    __syncthreads();
+    const int n_occ = occ_total;
+    auto rank_of = [&](int c) { return wbase[c >> 5] + __popc(bits[c >> 5] & ((1u << (c & 31)) - 1u)); };
+
+    // 3. particles per occupied cell
+    if (through_lds) {
+        for (int idx = tid; idx < P; idx += kSegBlock) {
+            const int r = rank_of(lrank[idx]);
+            lrank[idx] = (unsigned short)r;
+            atomicAdd(&cnt[r], 1);
+        }
+    } else {
+        for (int k0 = a + tid; k0 < e; k0 += kSegUnroll * kSegBlock) {
+            float4 v[kSegUnroll];
+#pragma unroll
+            for (int q = 0; q < kSegUnroll; ++q)
+                if (k0 + q * kSegBlock < e) v[q] = p.staging2[k0 + q * kSegBlock];
+#pragma unroll
+            for (int q = 0; q < kSegUnroll; ++q)
+                if (k0 + q * kSegBlock < e) atomicAdd(&cnt[rank_of(staged_cell(p, v[q]) - cell0)], 1);
+        }
+    }
+    __syncthreads();
+
+    // 4. exclusive prefix over the occupied cells (local slots)
+    {
+        const int per = (n_occ + kSegBlock - 1) / kSegBlock;
+        const int k0 = tid * per;
+        const int k1 = min(k0 + per, n_occ);
         int sum = 0;
-        if (owns)
-            for (int q = 0; q < per; ++q) sum += cnt[pad_idx(c0 + q)];
+        for (int k = k0; k < k1; ++k) sum += cnt[k];
         int total;
         int run = block_excl_scan<kSegBlock>(sum, lds, &total);
-        if (owns)
-            for (int q = 0; q < per; ++q) {
-                const int i = pad_idx(c0 + q);
-                const int v = cnt[i];
-                cnt[i] = run;
-                run += v;
-            }
-        if (tid == 0) cnt[sentinel] = P;
+        for (int k = k0; k < k1; ++k) {
+            const int v = cnt[k];
+            cnt[k] = run;
+            run += v;
+        }
     }
     __syncthreads();
 
-    // 3. occupancy words, starts of the occupied cells, dense work items (64
-    //    consecutive cells per wave step, so lane 0 of a step owns two words)
+    // 5. cell starts, dense work items
     {
         const int lane = lane_id();
-        const int groups = seg_cells >> 6;
-        for (int c = tid; c < seg_cells; c += kSegBlock) {
-            const unsigned long long bits = __ballot(cnt[pad_idx(c + 1)] != cnt[pad_idx(c)]);
-            if (lane == 0) gocc[c >> 6] = __popcll(bits);
-        }
-        __syncthreads();
-        {
-            const int v = tid < groups ? gocc[tid] : 0;   // at most 256 groups
-            int n_occ;
-            const int run = block_excl_scan<kSegBlock>(v, lds, &n_occ);
-            if (tid < groups) gocc[tid] = run;
-            if (tid == 0 && n_occ < P) p.cstart[a + n_occ] = e;
-        }
-        __syncthreads();
-        for (int c = tid; c < seg_cells; c += kSegBlock) {
-            const int st = cnt[pad_idx(c)];
-            const int v = cnt[pad_idx(c + 1)] - st;
-            const int start = a + st;
-            const int gc = cell0 + c;
-            const unsigned long long bits = __ballot(v > 0);
-            const int base = a + gocc[c >> 6];
-            if (v > 0) p.cstart[base + __popcll(bits & ((1ull << lane) - 1ull))] = start;
-            if (lane == 0) {
-                const unsigned lo = (unsigned)bits, hi = (unsigned)(bits >> 32);
-                *reinterpret_cast<uint4 *>(p.occ + (gc >> 5)) =
-                    make_uint4(lo, (unsigned)base, hi, (unsigned)(base + __popc(lo)));
+        for (int kb = 0; kb < n_occ; kb += kSegBlock) {
+            const int k = kb + tid;
+            int v = 0, start = 0;
+            if (k < n_occ) {
+                const int st = cnt[k];
+                v = (k + 1 < n_occ ? cnt[k + 1] : P) - st;
+                start = a + st;
+                p.cstart[a + k] = start;
             }
-            const int chunks = (v >= p.dense_min && v > 0) ? (v + 63) >> 6 : 0;
+            const int chunks = (k < n_occ && v >= p.dense_min) ? (v + 63) >> 6 : 0;
             if (__ballot(chunks > 0)) {
                 const int cincl = wave_incl_scan(chunks);
                 const int wave_items = __shfl(cincl, 63, 64);
@@ -488,6 +506,16 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
                 if (lane == 63) slot = (int)atomicAdd(&p.counters->n_items, (unsigned)wave_items);
                 slot = __shfl(slot, 63, 64) + cincl - chunks;
                 if (chunks) {
+                    // the word holding rank k: the last one whose base is at most k
+                    int lo = 0, hi = words - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (wbase[mid] <= k) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    unsigned m = bits[lo];
+                    for (int t = k - wbase[lo]; t > 0; --t) m &= m - 1u;   // drop the lower occupied cells
+                    const int gc = cell0 + (lo << 5) + (__ffs(m) - 1);
                     const int bx = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, start);
                     for (int q = 0; q < v; q += 64, ++slot)
                         if (slot < p.max_items) p.items[slot] = make_int4(gc, start + q, bx, 0);
@@ -504,11 +532,11 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     }
     __syncthreads();
 
-    // 4. placement: the slot order in LDS (cells known from step 1), or direct writes
+    // 6. placement: the slot order in LDS (ranks known from step 3), or direct writes
     bool bad = false;
     if (through_lds) {
         for (int idx = tid; idx < P; idx += kSegBlock) {
-            const int local = atomicAdd(&cnt[pad_idx(lcell[idx])], 1);
+            const int local = atomicAdd(&cnt[lrank[idx]], 1);
             if ((unsigned)local >= (unsigned)P) bad = true;
             else order[local] = (unsigned short)idx;
         }
@@ -522,7 +550,7 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
         for (int q = 0; q < kSegUnroll; ++q) {
             const int k = k0 + q * kSegBlock;
             if (k >= e) continue;
-            const int local = atomicAdd(&cnt[pad_idx(staged_cell(p, v[q]) - cell0)], 1);
+            const int local = atomicAdd(&cnt[rank_of(staged_cell(p, v[q]) - cell0)], 1);
             if ((unsigned)local >= (unsigned)P) {
                 bad = true;
                 continue;
