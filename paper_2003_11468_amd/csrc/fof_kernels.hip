@@ -366,6 +366,8 @@ constexpr int kSegBlock = 512;
 constexpr int kSegWaves = kSegBlock / 64;
 constexpr int kSegUnroll = 4;            // particles in flight per thread
 constexpr int kOrderCap = 4096;          // segments up to this many particles are placed through LDS
+constexpr int kCntCap = 4096;            // occupied cells counted at once (a window of ranks)
+static_assert(kCntCap >= kOrderCap, "a segment placed through LDS is one window");
 
 // One work-group per segment of 2^seg_shift consecutive cells, whose P
 // particles own sorted slots [a, a + P) (seg_end). Its work grows with P and
@@ -379,6 +381,9 @@ constexpr int kOrderCap = 4096;          // segments up to this many particles a
 //     here when the segment has fewer occupied cells than particles, else it
 //     is the next segment's first entry (or the final sentinel), which is e
 //     too;
+// Steps 3-6 run per window of kCntCap ranks, so the LDS does not grow with
+// the segment's cells (one window unless a segment placed directly has more
+// occupied cells than that):
 //  3. particle count per occupied cell, indexed by rank;
 //  4. exclusive prefix over the occupied cells (thread t owns a run);
 //  5. cell starts out, and dense link work items {cell, first home particle,
@@ -389,14 +394,11 @@ constexpr int kOrderCap = 4096;          // segments up to this many particles a
 //     written in slot order (coalesced), otherwise written directly.
 // A slot outside [0, P) cannot happen with consistent counts; it is latched
 // as error bit 1 instead of being written.
-// kLog2: the largest segment (2^kLog2 cells) the LDS of this instance holds;
-// smaller LDS lets more work-groups share a compute unit.
-template <int kLog2>
 __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
 {
-    constexpr int kWordsMax = (1 << kLog2) >> 5;
+    constexpr int kWordsMax = (1 << kSegLog2Max) >> 5;
     static_assert(kWordsMax <= kSegBlock, "one occupancy word per thread");
-    __shared__ int cnt[1 << kLog2];                  // per occupied cell: count, start, then cursor
+    __shared__ int cnt[kCntCap];                     // per occupied cell of a window: count, start, cursor
     __shared__ unsigned bits[kWordsMax];             // occupancy of the segment's cells
     __shared__ int wbase[kWordsMax];                 // occupied cells before each word
     __shared__ unsigned short order[kOrderCap];
@@ -443,126 +445,128 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
             occ_total = n_occ;
             if (n_occ < P) p.cstart[a + n_occ] = e;
         }
-        for (int k = tid; k < n_occ; k += kSegBlock) cnt[k] = 0;
     }
     __syncthreads();
     const int n_occ = occ_total;
     auto rank_of = [&](int c) { return wbase[c >> 5] + __popc(bits[c >> 5] & ((1u << (c & 31)) - 1u)); };
 
-    // 3. particles per occupied cell
-    if (through_lds) {
-        for (int idx = tid; idx < P; idx += kSegBlock) {
-            const int r = rank_of(lrank[idx]);
-            lrank[idx] = (unsigned short)r;
-            atomicAdd(&cnt[r], 1);
-        }
-    } else {
-        for (int k0 = a + tid; k0 < e; k0 += kSegUnroll * kSegBlock) {
-            float4 v[kSegUnroll];
-#pragma unroll
-            for (int q = 0; q < kSegUnroll; ++q)
-                if (k0 + q * kSegBlock < e) v[q] = p.staging2[k0 + q * kSegBlock];
-#pragma unroll
-            for (int q = 0; q < kSegUnroll; ++q)
-                if (k0 + q * kSegBlock < e) atomicAdd(&cnt[rank_of(staged_cell(p, v[q]) - cell0)], 1);
-        }
-    }
-    __syncthreads();
+    // 3.-6. per window of kCntCap ranks: one window, unless the segment is
+    // placed directly and has more occupied cells than that (then every
+    // window reads the segment's particles again)
+    int slot0 = 0;   // local slot of the window's first particle
+    bool bad = false;
+    for (int r0 = 0; r0 < n_occ; r0 += kCntCap) {
+        const int nw = min(kCntCap, n_occ - r0);
+        for (int k = tid; k < nw; k += kSegBlock) cnt[k] = 0;
+        __syncthreads();
 
-    // 4. exclusive prefix over the occupied cells (local slots)
-    {
-        const int per = (n_occ + kSegBlock - 1) / kSegBlock;
-        const int k0 = tid * per;
-        const int k1 = min(k0 + per, n_occ);
-        int sum = 0;
-        for (int k = k0; k < k1; ++k) sum += cnt[k];
-        int total;
-        int run = block_excl_scan<kSegBlock>(sum, lds, &total);
-        for (int k = k0; k < k1; ++k) {
-            const int v = cnt[k];
-            cnt[k] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
-
-    // 5. cell starts, dense work items
-    {
-        const int lane = lane_id();
-        for (int kb = 0; kb < n_occ; kb += kSegBlock) {
-            const int k = kb + tid;
-            int v = 0, start = 0;
-            if (k < n_occ) {
-                const int st = cnt[k];
-                v = (k + 1 < n_occ ? cnt[k + 1] : P) - st;
-                start = a + st;
-                p.cstart[a + k] = start;
+        // 3. particles per occupied cell of the window
+        if (through_lds) {   // a single window: n_occ <= P <= kOrderCap <= kCntCap
+            for (int idx = tid; idx < P; idx += kSegBlock) {
+                const int r = rank_of(lrank[idx]);
+                lrank[idx] = (unsigned short)r;
+                atomicAdd(&cnt[r], 1);
             }
-            const int chunks = (k < n_occ && v >= p.dense_min) ? (v + 63) >> 6 : 0;
-            if (__ballot(chunks > 0)) {
-                const int cincl = wave_incl_scan(chunks);
-                const int wave_items = __shfl(cincl, 63, 64);
-                int slot = 0;
-                if (lane == 63) slot = (int)atomicAdd(&p.counters->n_items, (unsigned)wave_items);
-                slot = __shfl(slot, 63, 64) + cincl - chunks;
-                if (chunks) {
-                    // the word holding rank k: the last one whose base is at most k
-                    int lo = 0, hi = words - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (wbase[mid] <= k) lo = mid;
-                        else hi = mid - 1;
+        } else {
+            for (int k = a + tid; k < e; k += kSegBlock) {
+                const int r = rank_of(staged_cell(p, p.staging2[k]) - cell0) - r0;
+                if ((unsigned)r < (unsigned)nw) atomicAdd(&cnt[r], 1);
+            }
+        }
+        __syncthreads();
+
+        // 4. exclusive prefix over the window's occupied cells (local slots)
+        int total;
+        {
+            const int per = (nw + kSegBlock - 1) / kSegBlock;
+            const int k0 = tid * per;
+            const int k1 = min(k0 + per, nw);
+            int sum = 0;
+            for (int k = k0; k < k1; ++k) sum += cnt[k];
+            int run = slot0 + block_excl_scan<kSegBlock>(sum, lds, &total);
+            for (int k = k0; k < k1; ++k) {
+                const int v = cnt[k];
+                cnt[k] = run;
+                run += v;
+            }
+        }
+        __syncthreads();
+
+        // 5. cell starts, dense work items
+        {
+            const int lane = lane_id();
+            for (int kb = 0; kb < nw; kb += kSegBlock) {
+                const int k = kb + tid;
+                int v = 0, start = 0;
+                if (k < nw) {
+                    const int st = cnt[k];
+                    v = (k + 1 < nw ? cnt[k + 1] : slot0 + total) - st;
+                    start = a + st;
+                    p.cstart[a + r0 + k] = start;
+                }
+                const int chunks = (k < nw && v >= p.dense_min) ? (v + 63) >> 6 : 0;
+                if (__ballot(chunks > 0)) {
+                    const int cincl = wave_incl_scan(chunks);
+                    const int wave_items = __shfl(cincl, 63, 64);
+                    int slot = 0;
+                    if (lane == 63) slot = (int)atomicAdd(&p.counters->n_items, (unsigned)wave_items);
+                    slot = __shfl(slot, 63, 64) + cincl - chunks;
+                    if (chunks) {
+                        // the word holding rank r0 + k: the last one whose base is at most that
+                        const int rk = r0 + k;
+                        int lo = 0, hi = words - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (wbase[mid] <= rk) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        unsigned m = bits[lo];
+                        for (int t = rk - wbase[lo]; t > 0; --t) m &= m - 1u;   // drop the lower occupied cells
+                        const int gc = cell0 + (lo << 5) + (__ffs(m) - 1);
+                        const int bx = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, start);
+                        for (int q = 0; q < v; q += 64, ++slot)
+                            if (slot < p.max_items) p.items[slot] = make_int4(gc, start + q, bx, 0);
                     }
-                    unsigned m = bits[lo];
-                    for (int t = k - wbase[lo]; t > 0; --t) m &= m - 1u;   // drop the lower occupied cells
-                    const int gc = cell0 + (lo << 5) + (__ffs(m) - 1);
-                    const int bx = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, start);
-                    for (int q = 0; q < v; q += 64, ++slot)
-                        if (slot < p.max_items) p.items[slot] = make_int4(gc, start + q, bx, 0);
                 }
             }
         }
-        // the final sentinel (the end of the last occupied cell, and the
-        // padding of 16-byte reads) and the two occupancy words after the last
-        // segment (the end of the last cell when the cells fill it exactly)
-        if (j + 1 == (int)gridDim.x && tid < 4) {
-            p.cstart[p.n + tid] = (int)p.n;
-            if (tid < 2) p.occ[((int64_t)gridDim.x << (p.seg_shift - 5)) + tid] = make_uint2(0u, (unsigned)p.n);
-        }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // 6. placement: the slot order in LDS (ranks known from step 3), or direct writes
-    bool bad = false;
-    if (through_lds) {
-        for (int idx = tid; idx < P; idx += kSegBlock) {
-            const int local = atomicAdd(&cnt[lrank[idx]], 1);
-            if ((unsigned)local >= (unsigned)P) bad = true;
-            else order[local] = (unsigned short)idx;
-        }
-    }
-    for (int k0 = a + tid; k0 < e && !through_lds; k0 += kSegUnroll * kSegBlock) {
-        float4 v[kSegUnroll];
-#pragma unroll
-        for (int q = 0; q < kSegUnroll; ++q)
-            if (k0 + q * kSegBlock < e) v[q] = p.staging2[k0 + q * kSegBlock];
-#pragma unroll
-        for (int q = 0; q < kSegUnroll; ++q) {
-            const int k = k0 + q * kSegBlock;
-            if (k >= e) continue;
-            const int local = atomicAdd(&cnt[rank_of(staged_cell(p, v[q]) - cell0)], 1);
-            if ((unsigned)local >= (unsigned)P) {
-                bad = true;
-                continue;
+        // 6. placement: the slot order in LDS (ranks known from step 3), or direct writes
+        if (through_lds) {
+            for (int idx = tid; idx < P; idx += kSegBlock) {
+                const int local = atomicAdd(&cnt[lrank[idx]], 1);
+                if ((unsigned)local >= (unsigned)P) bad = true;
+                else order[local] = (unsigned short)idx;
             }
-            const int dst = a + local;
-            const int i = __float_as_int(v[q].w);
-            p.sorted[dst] = make_float4(v[q].x, v[q].y, v[q].z, 0.0f);
-            p.perm[dst] = make_int2(i, i);
-            p.parent[dst] = dst;
-            p.gsize[dst] = 1;
-            p.kmap[dst] = p.stage2_k[k];
+        } else {
+            for (int k = a + tid; k < e; k += kSegBlock) {
+                const float4 v = p.staging2[k];
+                const int r = rank_of(staged_cell(p, v) - cell0) - r0;
+                if ((unsigned)r >= (unsigned)nw) continue;   // another window's particle
+                const int local = atomicAdd(&cnt[r], 1);
+                if ((unsigned)local >= (unsigned)P) {
+                    bad = true;
+                    continue;
+                }
+                const int dst = a + local;
+                const int i = __float_as_int(v.w);
+                p.sorted[dst] = make_float4(v.x, v.y, v.z, 0.0f);
+                p.perm[dst] = make_int2(i, i);
+                p.parent[dst] = dst;
+                p.gsize[dst] = 1;
+                p.kmap[dst] = p.stage2_k[k];
+            }
         }
+        slot0 += total;
+        __syncthreads();   // the next window clears cnt
+    }
+    // the final sentinel (the end of the last occupied cell, and the padding
+    // of 16-byte reads) and the two occupancy words after the last segment
+    // (the end of the last cell when the cells fill it exactly)
+    if (j + 1 == (int)gridDim.x && tid < 4) {
+        p.cstart[p.n + tid] = (int)p.n;
+        if (tid < 2) p.occ[((int64_t)gridDim.x << (p.seg_shift - 5)) + tid] = make_uint2(0u, (unsigned)p.n);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&p.counters->error, 2u);
     if (!through_lds) return;
@@ -895,11 +899,7 @@ hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t)
     if (p.n > 0)
         FOF_TIMED(K_SEG_SCATTER, hipLaunchKernelGGL(k_seg_scatter, dim3(seg_tiles), dim3(kBlock), 0, stream, p));
     const dim3 grid((unsigned)p.n_segments), block(kSegBlock);
-    FOF_TIMED(K_CELL_SORT, {
-        if (p.seg_shift <= 12) hipLaunchKernelGGL(k_cell_sort<12>, grid, block, 0, stream, p);
-        else if (p.seg_shift == 13) hipLaunchKernelGGL(k_cell_sort<13>, grid, block, 0, stream, p);
-        else hipLaunchKernelGGL(k_cell_sort<kSegLog2Max>, grid, block, 0, stream, p);
-    });
+    FOF_TIMED(K_CELL_SORT, hipLaunchKernelGGL(k_cell_sort, grid, block, 0, stream, p));
     return hipGetLastError();
 }
 

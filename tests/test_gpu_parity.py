@@ -186,7 +186,9 @@ def test_cell_sort_segments(segment_log2):
     pos = synth.clustered(n, 23, 0, 0.7)
     for b, cf in ((0.2, 0.0), (0.4, 1.0), (0.2, 3.0)):
         assert_single(pos, synth.linking_length(b, n), cell_factor=cf, segment_log2=segment_log2)
-    for nside in (16, 32):
+    # about one particle per cell: segments of 2^13 and 2^14 cells hold more
+    # occupied cells than one counting window, so they are sorted in windows
+    for nside in (16, 32, 48):
         u = synth.uniform(nside ** 3, 29)
         lx = synth.linking_length(0.9, nside ** 3)
         assert oracle.cells_per_axis(nside ** 3, lx) == nside
