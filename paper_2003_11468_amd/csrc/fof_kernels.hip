@@ -600,23 +600,24 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
 // Section 4), as a maximum and a sum.
 __global__ void __launch_bounds__(kBlock) k_find_depth(Plan p)
 {
-    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < p.n; base += (int64_t)gridDim.x * kBlock) {
-        const int64_t s64 = base + threadIdx.x;
+    unsigned dmax = 0;
+    unsigned long long dsum = 0;
+    for (int64_t s64 = (int64_t)blockIdx.x * kBlock + threadIdx.x; s64 < p.n; s64 += (int64_t)gridDim.x * kBlock) {
         unsigned d = 0;
-        if (s64 < p.n) {
-            int r = (int)s64;
-            for (int q = p.parent[r]; q != r; q = p.parent[r]) {
-                r = q;
-                ++d;
-            }
+        int r = (int)s64;
+        for (int q = p.parent[r]; q != r; q = p.parent[r]) {
+            r = q;
+            ++d;
         }
-        unsigned dm = d;
-        for (int k = 32; k >= 1; k >>= 1) dm = max(dm, (unsigned)__shfl_xor((int)dm, k, 64));
-        const unsigned long long ds = wave_sum_u64(d);
-        if (lane_id() == 0) {
-            atomicMax(&p.counters->depth_max, dm);
-            atomicAdd(&p.counters->depth_sum, ds);
-        }
+        dmax = max(dmax, d);
+        dsum += d;
+    }
+    // one pair of atomics per wave, after its whole share of the particles
+    for (int k = 32; k >= 1; k >>= 1) dmax = max(dmax, (unsigned)__shfl_xor((int)dmax, k, 64));
+    dsum = wave_sum_u64(dsum);
+    if (lane_id() == 0) {
+        atomicMax(&p.counters->depth_max, dmax);
+        atomicAdd(&p.counters->depth_sum, dsum);
     }
 }
 
