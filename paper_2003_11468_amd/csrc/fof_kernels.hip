@@ -622,9 +622,15 @@ __global__ void __launch_bounds__(kBlock) k_find_depth(Plan p)
 }
 
 // Consecutive sorted particles often share their root, so the root updates of
-// runs of equal roots in a wave are combined before the atomics.
+// runs of equal roots in a wave are combined before the atomics. The run that
+// ends at the wave's last lane stays pending into the wave's next stretch of
+// particles and is merged with its first run when the root is the same: the
+// atomics on the root of one giant group (every particle of the box, in the
+// worst case) then come to one pair per wave instead of one per 64 particles.
 __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
 {
+    const int lane = lane_id();
+    int pend_key = -1, pend_m = INT_MAX, pend_c = 0;   // the same in every lane
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < p.n; base += (int64_t)gridDim.x * kBlock) {
         const int64_t s64 = base + threadIdx.x;
         int root_key = -1, m = INT_MAX, c = 0;
@@ -642,10 +648,34 @@ __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
                 c = 1;
             }
         }
-        if (wave_runs_min_add(root_key, m, c)) {
+        const int prev = __shfl_up(root_key, 1, 64);
+        const unsigned long long heads = __ballot(lane == 0 || prev != root_key);
+        const int last_head = 63 - __clzll((long long)heads);   // first lane of the run holding lane 63
+        const int key_first = __shfl(root_key, 0, 64), key_last = __shfl(root_key, 63, 64);
+        const bool head = wave_runs_min_add(root_key, m, c);
+        if (pend_key >= 0) {
+            if (pend_key == key_first) {
+                if (lane == 0) {   // lane 0 heads the first run
+                    m = min(m, pend_m);
+                    c += pend_c;
+                }
+            } else if (lane == 0) {
+                atomicMin(&p.perm[pend_key].y, pend_m);
+                atomicAdd(&p.gsize[pend_key], pend_c);
+            }
+        }
+        const int lm = __shfl(m, last_head, 64), lc = __shfl(c, last_head, 64);
+        if (head && lane != last_head) {
             atomicMin(&p.perm[root_key].y, m);
             atomicAdd(&p.gsize[root_key], c);
         }
+        pend_key = key_last;
+        pend_m = lm;
+        pend_c = lc;
+    }
+    if (pend_key >= 0 && lane == 0) {
+        atomicMin(&p.perm[pend_key].y, pend_m);
+        atomicAdd(&p.gsize[pend_key], pend_c);
     }
 }
 

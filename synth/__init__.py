@@ -15,6 +15,13 @@ Workloads (box side L = 1, linking length l_x = b x mean separation):
                    each from the clustered256 generator (60 % halos), its own
                    l_x = 0.2 / cbrt(N_b); seed 3, box b uses stream b.
 ``percolate1024``  N = 1024^3, 90 % in halos, counts on [20, 1e6], b = 0.5, seed 4.
+                   Its largest group holds about 1e4 particles: it does not percolate.
+``lattice1024``    N = 1024^3 on a cubic lattice of spacing s = 0.9 l_x, each site
+                   jittered by up to 2 % of s per axis, seed 5: every particle links
+                   exactly its six axis neighbours (at most 1.042 s < l_x = 1.111 s
+                   apart; diagonal neighbours stay at least 1.357 s apart), so the
+                   whole box is one group of 1024^3, the most contended input for
+                   the union-find.
 """
 from __future__ import annotations
 
@@ -60,6 +67,9 @@ def _load():
     lib.synth_clustered.argtypes = [ctypes.c_int64, ctypes.c_double, i64p, ctypes.c_int64,
                                     ctypes.c_uint32, ctypes.c_uint32, f32p]
     lib.synth_clustered.restype = None
+    lib.synth_lattice.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
+                                  ctypes.c_uint32, f32p]
+    lib.synth_lattice.restype = None
     lib.synth_box_sizes.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint32, i64p]
     lib.synth_box_sizes.restype = None
     _lib = lib
@@ -110,6 +120,15 @@ def clustered(n: int, seed: int, stream: int = 0, halo_frac: float = 0.6, m_min:
     return pos
 
 
+def jittered_lattice(side: int, jitter: float, seed: int, stream: int = 0, box: float = 1.0) -> np.ndarray:
+    """side^3 lattice sites of spacing box/side, each coordinate moved by a
+    uniform offset of up to `jitter` spacings, in shuffled order."""
+    pos = np.empty((side ** 3, 3), dtype=np.float32)
+    if side:
+        _load().synth_lattice(side, box, jitter, seed, stream, _ptr(pos, ctypes.c_float))
+    return pos
+
+
 def box_sizes(n_boxes: int, lo: float, hi: float, seed: int) -> np.ndarray:
     out = np.empty(n_boxes, dtype=np.int64)
     _load().synth_box_sizes(n_boxes, lo, hi, seed, _ptr(out, ctypes.c_int64))
@@ -154,6 +173,7 @@ RECIPES = {
     "clustered512": dict(kind="clustered", n=512 ** 3, b=0.2, seed=2, halo_frac=0.7, m_max=1e5),
     "batched256": dict(kind="batched", n_boxes=256, lo=1e3, hi=1e6, b=0.2, seed=3, halo_frac=0.6, m_max=1e5),
     "percolate1024": dict(kind="clustered", n=1024 ** 3, b=0.5, seed=4, halo_frac=0.9, m_max=1e6),
+    "lattice1024": dict(kind="lattice", side=1024, spacing_over_lx=0.9, jitter=0.02, seed=5),
 }
 
 
@@ -167,6 +187,12 @@ def make(name: str, n: int | None = None, n_boxes: int | None = None, size_scale
         n = r["n"] if n is None else n
         pos = clustered(n, r["seed"], 0, r["halo_frac"], 20.0, r["m_max"], 1.9)
         return _single(name, pos, r["b"], dict(r, n=n))
+    if r["kind"] == "lattice":
+        side = r["side"] if n is None else int(round(n ** (1.0 / 3.0)))
+        pos = jittered_lattice(side, r["jitter"], r["seed"])
+        lx = (1.0 / side) / r["spacing_over_lx"]
+        return Workload(name, pos, np.array([0, side ** 3], dtype=np.int64), np.array([1.0]), np.array([lx]),
+                        dict(r, side=side))
     nb = r["n_boxes"] if n_boxes is None else n_boxes
     sizes = box_sizes(nb, r["lo"], r["hi"], r["seed"])
     sizes = np.maximum(1, np.round(sizes * size_scale)).astype(np.int64)

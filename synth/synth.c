@@ -23,7 +23,7 @@
 #include <string.h>
 
 enum { TAG_HALO_MASS = 1, TAG_HALO_CENTRE = 2, TAG_HALO_PART = 3, TAG_BACKGROUND = 4,
-       TAG_PERMUTE = 5, TAG_BOX_SIZE = 6 };
+       TAG_PERMUTE = 5, TAG_BOX_SIZE = 6, TAG_LATTICE = 7 };
 
 /* Philox4x32-10: ten rounds of the S-box below, with the Weyl key schedule. */
 static void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
@@ -227,6 +227,30 @@ void synth_clustered(int64_t n, double L, const int64_t *counts, int64_t n_halos
     free(start);
     free(centre);
     free(scale);
+}
+
+/* A jittered cubic lattice: side^3 sites of spacing s = L / side, site
+ * (i, j, k) at ((i + 1/2 + d_x) s, (j + 1/2 + d_y) s, (k + 1/2 + d_z) s) with
+ * each d uniform on [-jitter, jitter), stored in shuffled order. */
+void synth_lattice(int64_t side, double L, double jitter, uint32_t seed, uint32_t stream, float *pos)
+{
+    const int64_t n = side * side * side;
+    const double s = L / (double)side;
+    perm_t perm;
+    perm_init(&perm, (uint64_t)n, seed, stream);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t w[4];
+        draw4(seed, stream, (uint64_t)k, TAG_LATTICE, w);
+        const double i = (double)(k % side), j = (double)((k / side) % side), l = (double)(k / (side * side));
+        const double x = (i + 0.5 + jitter * (2.0 * u24(w[0]) - 1.0)) * s;
+        const double y = (j + 0.5 + jitter * (2.0 * u24(w[1]) - 1.0)) * s;
+        const double z = (l + 0.5 + jitter * (2.0 * u24(w[2]) - 1.0)) * s;
+        uint64_t dst = perm_apply(&perm, (uint64_t)k);
+        pos[3 * dst + 0] = wrap_to_f32(x, L);
+        pos[3 * dst + 1] = wrap_to_f32(y, L);
+        pos[3 * dst + 2] = wrap_to_f32(z, L);
+    }
 }
 
 /* Box particle counts for the batched workload: round(exp(U[ln lo, ln hi])). */

@@ -7,7 +7,8 @@ are checked by invariants that hold at any size (labels are group minima,
 sizes count members, the group count is the number of roots) and by
 breadth-first search of the groups of sampled particles -- including the
 largest group -- which must have the GPU's label (its minimum), size and
-exact member set.
+exact member set. lattice1024 (1.07B on a jittered lattice) is one group by
+construction, which fixes every label and size.
 """
 from __future__ import annotations
 
@@ -119,3 +120,21 @@ def test_clustered512_full_size_invariants_and_sampled_groups():
 def test_percolate1024_full_size_invariants_and_sampled_groups():
     label, size, ng = _sampled_case("percolate1024", 1024)
     assert int(ng[0]) < 1024 ** 3
+
+
+# The most contended input: 1024^3 particles that form one group. Both link
+# orders, in the benchmark's kind of configuration (tuned over a few cell sizes).
+def test_lattice1024_is_one_group_under_both_link_orders():
+    w = synth.make("lattice1024")
+    pos = torch.from_numpy(w.pos).cuda()
+    cfg = tuned(pos, w, cell_factors=(0.0, 2.0), dense_mins=(32,))
+    for order in ("index", "random"):
+        f = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"], link_order=order)
+        try:
+            label, size, ng = f.run(pos, w.offsets, w.box, w.lx)
+            assert int(ng[0]) == 1, order
+            assert int(label.count_nonzero()) == 0, order
+            assert int(size[0]) == w.n and int(size.count_nonzero()) == 1, order
+        finally:
+            f.close()
+        torch.cuda.empty_cache()

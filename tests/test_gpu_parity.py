@@ -312,6 +312,21 @@ def test_randomised_linking_same_labels():
     assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and np.array_equal(ng, ref[2])
 
 
+# The contention input at a size the oracle handles: a jittered lattice that
+# is one group. Both link orders, both predicates, sparse and dense paths.
+def test_jittered_lattice_one_group_both_link_orders():
+    w = synth.make("lattice1024", n=64 ** 3)
+    ref = oracle.fof(w.pos, float(w.lx[0]))
+    assert ref[2] == 1
+    for order in ("index", "random"):
+        for predicate in PREDICATES:
+            for cf, dm in ((0.0, 0), (2.0, 4)):
+                lab, size, ng, st = gpu_run(w.pos, w.offsets, w.box, w.lx, predicate, cell_factor=cf, dense_min=dm,
+                                            stats=True, link_order=order)
+                assert np.array_equal(lab, ref[0]) and np.array_equal(size, ref[1]) and int(ng[0]) == 1
+                assert st["links"] >= w.n - 1
+
+
 # Find depth statistics: every non-root is at least one step from its root,
 # a forest of singletons has depth 0, and the sum is bounded by max x n.
 def test_find_depth_statistics():

@@ -45,3 +45,33 @@ def test_workload_shapes():
     w = synth.make("batched256", n_boxes=4, size_scale=0.01)
     assert w.n_boxes == 4 and w.offsets[-1] == len(w.pos)
     assert synth.linking_length(0.2, 256 ** 3) == 0.2 / 256
+
+
+def test_jittered_lattice_links_exactly_six_axis_neighbours():
+    """The contention input: one particle per lattice site within 2 % of a
+    spacing of its centre; by brute-force periodic distances every particle
+    has exactly six neighbours within l_x, so the box is one group (the
+    oracle agrees)."""
+    import oracle
+
+    side = 12
+    w = synth.make("lattice1024", n=side ** 3)
+    assert w.n == side ** 3 and abs(w.lx[0] - (1.0 / side) / 0.9) < 1e-15
+    p = w.pos.astype(np.float64)
+    s = 1.0 / side
+    site = np.floor(p / s).astype(np.int64)
+    key = (site[:, 2] * side + site[:, 1]) * side + site[:, 0]
+    assert np.array_equal(np.sort(key), np.arange(side ** 3))
+    assert np.abs(p / s - (site + 0.5)).max() <= 0.02 + 1e-5
+    d = p[:, None, :] - p[None, :, :]
+    d -= np.round(d)                                   # minimum image in the unit box
+    r2 = (d * d).sum(-1)
+    np.fill_diagonal(r2, np.inf)
+    near = r2 <= w.lx[0] ** 2
+    assert np.all(near.sum(1) == 6)
+    steps = np.abs(site[:, None, :] - site[None, :, :]) % side
+    steps = np.minimum(steps, side - steps).sum(-1)   # lattice (Manhattan) distance of the sites
+    assert np.all(steps[near] == 1)
+    w = synth.make("lattice1024", n=24 ** 3)
+    label, size, ng = oracle.fof(w.pos, float(w.lx[0]))
+    assert ng == 1 and not label.any() and size[0] == 24 ** 3
