@@ -222,6 +222,32 @@ def cpu_baseline(w):
                                     f"box, l_x x2; single-threaded C oracle, {dt:.1f} s"}
 
 
+def cpu_baseline_batched(wb, label, size, max_box: int = 50000):
+    """The oracle on a bounded sample of the batch: every box of at most
+    `max_box` particles (the larger boxes alone would keep one thread busy for
+    tens of seconds), boxes spread over the host's threads (one box per thread,
+    as many threads as the process may use, at most 16); also whether the
+    GPU's labels and sizes on those boxes equal the oracle's."""
+    import numpy as np
+
+    import oracle
+
+    sizes = np.diff(wb.offsets)
+    sel = np.nonzero(sizes <= max_box)[0]
+    pos = np.concatenate([wb.pos[wb.offsets[k]:wb.offsets[k + 1]] for k in sel])
+    off = np.concatenate([[0], np.cumsum(sizes[sel])]).astype(np.int64)
+    lab = np.concatenate([label[wb.offsets[k]:wb.offsets[k + 1]] for k in sel])
+    siz = np.concatenate([size[wb.offsets[k]:wb.offsets[k + 1]] for k in sel])
+    threads = max(1, min(16, len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16"))))
+    t0 = time.perf_counter()
+    ref = oracle.fof_boxes(pos, off, np.asarray(wb.box)[sel], np.asarray(wb.lx)[sel], threads=threads)
+    dt = time.perf_counter() - t0
+    exact = bool(np.array_equal(lab, ref[0]) and np.array_equal(siz, ref[1]))
+    return {"value": int(off[-1]) / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"the {len(sel)} boxes of batched256 with at most {max_box} particles ({int(off[-1])} "
+                      f"particles), one box per thread on {threads} host threads, {dt:.1f} s"}, exact
+
+
 def main():
     args = parse()
     if args.ingest_counters:
@@ -384,10 +410,15 @@ def main():
         torch.cuda.synchronize()
         msb = e0.elapsed_time(e1) / nb_steps
         lab_b = lb.cpu().numpy()
+        size_b = sb.cpu().numpy()
         fb.close()
         batched = {"workload": "batched256", "n_boxes": wb.n_boxes, "n_particles": wb.n,
                    "fp32_graph": {"value": wb.n / (msb * 1e-3), "ms_per_step": msb,
                                   "cell_factor": cfgb["cell_factor"], "dense_min": cfgb["dense_min"]}}
+        if not args.no_cpu_baseline:
+            log("cpu baseline on batched256 (oracle, one box per host thread)")
+            batched["cpu_baseline_parallel"], exact = cpu_baseline_batched(wb, lab_b, size_b)
+            batched["exact_vs_oracle_on_sample"] = exact
         if not args.no_plain:
             # plain path: FP64 predicate, one launch sequence per box, no graph
             log("timing batched fp64 per box")
