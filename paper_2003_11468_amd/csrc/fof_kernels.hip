@@ -413,6 +413,18 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     const int P = e - a;
     const int tid = (int)threadIdx.x;
     const bool through_lds = P <= kOrderCap;
+    const int seg_cells = words << 5;
+    bool bad = false;
+    // the segment's cell of a staged particle; a cell outside the segment
+    // cannot happen with a consistent partition and is latched, not used
+    auto local_cell = [&](const float4 &v) {
+        const int c = staged_cell(p, v) - cell0;
+        if ((unsigned)c >= (unsigned)seg_cells) {
+            bad = true;
+            return 0;
+        }
+        return c;
+    };
     for (int w = tid; w < words; w += kSegBlock) bits[w] = 0u;
     __syncthreads();
 
@@ -425,7 +437,7 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
 #pragma unroll
         for (int q = 0; q < kSegUnroll; ++q)
             if (k0 + q * kSegBlock < e) {
-                const int c = staged_cell(p, v[q]) - cell0;
+                const int c = local_cell(v[q]);
                 atomicOr(&bits[c >> 5], 1u << (c & 31));
                 if (through_lds) lrank[k0 + q * kSegBlock - a] = (unsigned short)c;
             }
@@ -454,7 +466,6 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     // placed directly and has more occupied cells than that (then every
     // window reads the segment's particles again)
     int slot0 = 0;   // local slot of the window's first particle
-    bool bad = false;
     for (int r0 = 0; r0 < n_occ; r0 += kCntCap) {
         const int nw = min(kCntCap, n_occ - r0);
         for (int k = tid; k < nw; k += kSegBlock) cnt[k] = 0;
@@ -469,7 +480,7 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
             }
         } else {
             for (int k = a + tid; k < e; k += kSegBlock) {
-                const int r = rank_of(staged_cell(p, p.staging2[k]) - cell0) - r0;
+                const int r = rank_of(local_cell(p.staging2[k])) - r0;
                 if ((unsigned)r < (unsigned)nw) atomicAdd(&cnt[r], 1);
             }
         }
@@ -542,7 +553,7 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
         } else {
             for (int k = a + tid; k < e; k += kSegBlock) {
                 const float4 v = p.staging2[k];
-                const int r = rank_of(staged_cell(p, v) - cell0) - r0;
+                const int r = rank_of(local_cell(v)) - r0;
                 if ((unsigned)r >= (unsigned)nw) continue;   // another window's particle
                 const int local = atomicAdd(&cnt[r], 1);
                 if ((unsigned)local >= (unsigned)P) {
