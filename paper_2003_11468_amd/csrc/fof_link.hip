@@ -359,30 +359,27 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
             const int rb0 = c - cx;
             // Boundaries of the own row and the four neighbour rows (dy, dz) =
             // (1, 0), (-1, 1), (0, 1), (1, 1): with the own cell these hold the
-            // 13 half-shell cells. All are requested before any is used.
-            // Occupancy words first (bits and rank base per 32 cells, a small
-            // array that stays in cache): boundaries are read only for rows
-            // with a particle, from the starts of the occupied cells.
+            // 13 half-shell cells. Occupancy words (bits and rank base per 32
+            // cells, a small array that stays in cache) give the rank of each
+            // cell among the occupied ones, and cstart the boundaries.
             const uint2 *occ = p.occ;
-            auto rank_in = [](uint2 w, int cell_index) {
-                return (int)w.y + __popc(w.x & ((1u << (cell_index & 31)) - 1u));
+            typedef unsigned uint4a8 __attribute__((ext_vector_type(4), aligned(8)));
+            typedef int int4a4 __attribute__((ext_vector_type(4), aligned(4)));
+            auto rank_in = [](unsigned bits, unsigned base, int cell_index) {
+                return (int)base + __popc(bits & ((1u << (cell_index & 31)) - 1u));
             };
             auto span = [&](int cell_index, int &s0, int &s1) {   // left at 0, 0 for an empty cell
                 const uint2 w = occ[cell_index >> 5];
                 if ((w.x >> (cell_index & 31)) & 1u) {
-                    const int r = rank_in(w, cell_index);
+                    const int r = rank_in(w.x, w.y, cell_index);
                     s0 = cst[r];
                     s1 = cst[r + 1];
                 }
             };
-            const int r_own = rank_in(occ[c >> 5], c);   // the own cell holds s
-            const int own_start = cst[r_own], own_end = cst[r_own + 1];
             const int nxp = cx + 1 < nc ? cx + 1 : 0;
-            int nxt_start = 0, nxt_end = 0;
-            span(rb0 + nxp, nxt_start, nxt_end);
             const bool inner = cx >= 1 && cx + 1 < nc;
             const int rdy[4] = {1, -1, 0, 1}, rdz[4] = {0, 1, 1, 1};
-            int st[4][3], en[4][3], yz[4];
+            int rb[4], yz[4], c0[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int ny = cy + rdy[r], nz = cz + rdz[r], code = 0;
@@ -390,34 +387,68 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
                 else if (ny < 0) { ny += nc; code |= 1 << 2; }
                 if (nz >= nc) { nz -= nc; code |= 2 << 4; }
                 yz[r] = code;
-                const int rb = cb + (nz * nc + ny) * nc;
+                rb[r] = cb + (nz * nc + ny) * nc;
+                c0[r] = rb[r] + (inner ? cx - 1 : 0);
+            }
+            // Two rounds of loads, each issued whole before any of its results
+            // is used, with no branch among them: first the occupancy words of
+            // the own cell and of each row (two words each, so cells across a
+            // word boundary are covered), then, from the ranks, one 16-byte
+            // read of cell starts for the own cell and for each row. Every
+            // address is in range whatever the bits: a rank is at most n and
+            // cstart has n + 4 entries; a word index is at most the last one
+            // plus one, inside the two words of padding.
+            const uint4a8 wo = *reinterpret_cast<const uint4a8 *>(occ + (c >> 5));
+            uint4a8 wr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wr[r] = *reinterpret_cast<const uint4a8 *>(occ + (c0[r] >> 5));
+            const int4a4 qo = *reinterpret_cast<const int4a4 *>(cst + rank_in(wo.x, wo.y, c));   // the own cell holds s
+            int4a4 qr[4];
+            unsigned mr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                mr[r] = (unsigned)((((uint64_t)wr[r].x | ((uint64_t)wr[r].z << 32)) >> (c0[r] & 31)) & 7u);
+                qr[r] = *reinterpret_cast<const int4a4 *>(cst + rank_in(wr[r].x, wr[r].y, c0[r]));
+            }
+            const int own_start = qo.x, own_end = qo.y;
+            int nxt_start = 0, nxt_end = 0;
+            if (nxp && ((c ^ (c + 1)) >> seg_shift) == 0) {
+                // the next cell in the same segment: its entries follow the own cell's
+                const unsigned nbits = ((c + 1) & 31) ? wo.x : wo.z;
+                if ((nbits >> ((c + 1) & 31)) & 1u) {
+                    nxt_start = qo.y;
+                    nxt_end = qo.z;
+                }
+            } else {
+                span(rb0 + nxp, nxt_start, nxt_end);
+            }
+            int st[4][3], en[4][3];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
 #pragma unroll
                 for (int e = 0; e < 3; ++e) st[r][e] = en[r][e] = 0;
-                if (inner) {
-                    const int c0 = rb + cx - 1;
-                    const uint2 w0 = occ[c0 >> 5], w1 = occ[(c0 >> 5) + 1];
-                    const unsigned m = (unsigned)(((uint64_t)w0.x | ((uint64_t)w1.x << 32)) >> (c0 & 31)) & 7u;
-                    if (m && ((c0 ^ (c0 + 2)) >> seg_shift) == 0) {
-                        // the three cells in one segment: their occupied cells have
-                        // consecutive entries, so one 16-byte read holds every boundary
-                        typedef int int4a4 __attribute__((ext_vector_type(4), aligned(4)));
-                        const int4a4 q = *reinterpret_cast<const int4a4 *>(cst + rank_in(w0, c0));
-                        auto pick = [&](unsigned k) { return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w)); };
-                        const unsigned o1 = m & 1u, o2 = o1 + ((m >> 1) & 1u), o3 = o2 + (m >> 2);
-                        const int b1 = pick(o1), b2 = pick(o2);
-                        st[r][0] = q.x; en[r][0] = b1;
-                        st[r][1] = b1; en[r][1] = b2;
-                        st[r][2] = b2; en[r][2] = pick(o3);
-                    } else if (m) {
+                const unsigned m = mr[r];
+                if (inner && ((c0[r] ^ (c0[r] + 2)) >> seg_shift) == 0) {
+                    // the three cells in one segment: their occupied cells have
+                    // consecutive entries, so the 16-byte read holds every boundary
+                    const int4a4 q = qr[r];
+                    auto pick = [&](unsigned k) { return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w)); };
+                    const unsigned o1 = m & 1u, o2 = o1 + ((m >> 1) & 1u), o3 = o2 + (m >> 2);
+                    const int b1 = pick(o1), b2 = pick(o2);
+                    st[r][0] = q.x; en[r][0] = b1;
+                    st[r][1] = b1; en[r][1] = b2;
+                    st[r][2] = b2; en[r][2] = pick(o3);
+                } else if (inner) {
+                    if (m) {
 #pragma unroll
-                        for (int e = 0; e < 3; ++e) span(c0 + e, st[r][e], en[r][e]);
+                        for (int e = 0; e < 3; ++e) span(c0[r] + e, st[r][e], en[r][e]);
                     }
                 } else {
 #pragma unroll
                     for (int e = 0; e < 3; ++e) {
                         int nx = cx - 1 + e;
                         nx += nx < 0 ? nc : (nx >= nc ? -nc : 0);
-                        span(rb + nx, st[r][e], en[r][e]);
+                        span(rb[r] + nx, st[r][e], en[r][e]);
                     }
                 }
             }
