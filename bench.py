@@ -485,8 +485,9 @@ def main():
         "n_groups": groups,
         "catalogue": cat,
         "kernels": passes,
-        "stats": {k: st[k] for k in ("pair_tests", "sparse_pair_tests", "links", "band_hits", "cas_retries",
-                                     "queued_links", "dense_items")},
+        "stats": dict({k: st[k] for k in ("pair_tests", "sparse_pair_tests", "links", "band_hits", "cas_retries",
+                                          "queued_links", "dense_items", "find_depth_max")},
+                      find_depth_mean=st["find_depth_sum"] / max(1, n), largest_group=int(size32.max(initial=0))),
         "guard_band_hit_fraction": {"per_test": st["band_hits"] / max(1, st["pair_tests"]),
                                     "per_link": st["band_hits"] / max(1, st["links"])},
         "roofline": roofline,
