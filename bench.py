@@ -200,7 +200,19 @@ def timed_steps(torch, fof, f, pos, w, steps, warmup, label, size):
     end = event(torch, f.stream)
     torch.cuda.synchronize()
     kt = f.kernel_times()
-    return start.elapsed_time(end) / steps, {k: (ms / max(1, c), c) for k, (ms, c) in kt.items() if c}
+    # the spread of single steps, from as many steps again with an event
+    # after each (kept out of the timed region above)
+    marks = [event(torch, f.stream)]
+    for _ in range(steps):
+        fof.fof_build_cells(f.ctx, pos, w.offsets, w.box, w.lx)
+        fof.fof_link(f.ctx)
+        fof.fof_finalize(f.ctx, label, size)
+        marks.append(event(torch, f.stream))
+    torch.cuda.synchronize()
+    f.kernel_times()
+    per_step = [a.elapsed_time(b) for a, b in zip(marks[:-1], marks[1:])]
+    return (start.elapsed_time(end) / max(1, steps), {k: (ms / max(1, c), c) for k, (ms, c) in kt.items() if c},
+            per_step)
 
 
 def cpu_baseline(w):
@@ -283,7 +295,7 @@ def main():
     f = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"], timings=True)
     label, size = f.outputs(n)
     log(f"timing fp32_filter cell_factor={cfg['cell_factor']} dense_min={cfg['dense_min']}")
-    ms, kern = timed_steps(torch, fof, f, pos, w, args.steps, args.warmup, label, size)
+    ms, kern, per_step = timed_steps(torch, fof, f, pos, w, args.steps, args.warmup, label, size)
     groups = int(f.n_groups(w.n_boxes).sum())
     # group catalogue of the last step (groups of more than 20 members, the paper's cut), not in the step
     cat = {"min_size": 21}
@@ -334,7 +346,7 @@ def main():
         fd = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"], timings=True,
                      domains=args.domains)
         ld, sd = fd.outputs(n)
-        msd, _ = timed_steps(torch, fof, fd, pos, w, max(3, args.steps // 2), 1, ld, sd)
+        msd, _, _ = timed_steps(torch, fof, fd, pos, w, max(3, args.steps // 2), 1, ld, sd)
         fd.close()
         fds = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"], stats=True,
                       domains=args.domains)
@@ -355,7 +367,7 @@ def main():
         f64 = fof.FoF("fp64", cell_factor=cfg64["cell_factor"], dense_min=cfg64["dense_min"], timings=True)
         l64, s64 = f64.outputs(n)
         log("timing fp64")
-        ms64, kern64 = timed_steps(torch, fof, f64, pos, w, max(3, args.steps // 2), 1, l64, s64)
+        ms64, kern64, _ = timed_steps(torch, fof, f64, pos, w, max(3, args.steps // 2), 1, l64, s64)
         exact = bool(np.array_equal(l64.cpu().numpy(), lab32) and np.array_equal(s64.cpu().numpy(), size32))
         plain = {"value": n / (ms64 * 1e-3), "unit": "particles/s", "ms_per_step": ms64,
                  "cell_factor": cfg64["cell_factor"], "dense_min": cfg64["dense_min"],
@@ -473,6 +485,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_median": statistics.median(per_step) if per_step else None,
+        "ms_per_step_std": statistics.stdev(per_step) if len(per_step) > 1 else 0.0,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
