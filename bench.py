@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 import time
@@ -34,7 +35,7 @@ FP32_VALU_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 FLOP_PER_PAIR_TEST = 8            # 3 sub, 3 mul, 2 add (an FMA counts as mul + add)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2003_11468_amd", "csrc", f)
-                  for f in ("fof_kernels.hip", "fof_link.hip", "fof_device.h")]
+                  for f in ("fof_kernels.hip", "fof_link.hip", "fof_device.h", "fof_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -93,10 +94,18 @@ def event(torch, stream):
     return e
 
 
+def code_only(text: str) -> str:
+    """Source text without its comments and with runs of white space folded,
+    so that an edit to comments alone keeps the hash of the kernels."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_sha() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(f, "rb").read())
+        h.update(code_only(open(f).read()).encode())
     return h.hexdigest()[:16]
 
 

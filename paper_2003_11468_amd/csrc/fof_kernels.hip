@@ -6,7 +6,9 @@
 // The counting sort into cells runs in three levels so that no pass scatters
 // over the whole array and no pass counts cells in global memory. Cells are
 // grouped into at most 256 buckets of consecutive cell indices, and buckets
-// into segments of at most 2^14 cells (a segment's counts fit in LDS).
+// into segments of at most 2^14 cells (a segment's occupancy bits fit in LDS).
+// Cells are indexed by rank: per 32 cells an occupancy word {bits, rank base},
+// and the first slot of each occupied cell only (no array per cell).
 //   clear          zero the segment counts, group counters and error word
 //   bucket_hist    per tile of 2048 input particles: validate coordinates,
 //                  bucket histogram in LDS
@@ -19,14 +21,16 @@
 //   seg_scan       exclusive prefix over the segment counts
 //   seg_scatter    sort each such tile by segment in LDS and write it out as
 //                  runs: the segment order
-//   cell_sort      one work-group per segment: count its cells in LDS, scan,
-//                  write the cell starts, occupancy bits and dense link work
-//                  items, then place every particle in cell order (x, y, z as
-//                  float4) with its original index, and seed the union-find
-//                  forest
+//   cell_sort      one work-group per segment: occupancy bits and rank bases,
+//                  counts of the occupied cells in LDS, scan, write the
+//                  occupancy words, the starts of the occupied cells and the
+//                  dense link work items, then place every particle in cell
+//                  order (x, y, z as float4) with its original index, and seed
+//                  the union-find forest
 //   link           (fof_link.hip) cell-pair link search + lock-free union-find
 //   flatten  pointer jumping to the root; group minimum original index
-//            (atomic min) and member count (atomic add) at the root
+//            (atomic min) and member count (atomic add) at the root, combined
+//            over runs of equal roots (a wave's last run carries over)
 //   resolve  label and size per sorted slot, stored at its staging slot
 //            (writes stay in bucket windows); per-box group counts
 //   gather   back into input order (reads are runs of each tile's buckets)

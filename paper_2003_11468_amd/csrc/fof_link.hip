@@ -29,7 +29,9 @@
 // staged candidate carries the root found when it was staged. A linked pair
 // whose two cached roots agree is already in one group and is skipped: both
 // roots were observed as members of the respective groups, and groups only
-// grow. Otherwise the lane hooks the larger root under the smaller (CAS).
+// grow. Otherwise the lane hooks the root of lower priority under the other
+// (CAS): by index, the larger under the smaller, or by a fixed pseudo-random
+// priority (randomised linking).
 #include "fof_device.h"
 
 namespace fof {
