@@ -1,0 +1,75 @@
+"""Host logic of bench.py (no GPU): the one-GPU contract, the kernel source
+hash behind the traffic table, and the ingestion of rocprofv3 counter runs."""
+from __future__ import annotations
+
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr and r.stdout == ""
+
+
+def test_source_hash_ignores_comments_only():
+    code = "int f(int a) { return a + 1; } // one\n/* two\n three */ int g;\n"
+    assert bench.code_only(code) == bench.code_only("int f(int a) {\n  return a + 1;\n}\n// other\nint g;")
+    assert bench.code_only(code) != bench.code_only(code.replace("a + 1", "a + 2"))
+    assert len(bench.source_sha()) == 16
+
+
+def _write(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_counter_ingestion_scales_by_the_calibration(tmp_path, monkeypatch):
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    kname = "void fof::(anonymous namespace)::k_gather(fof::Plan)"
+    fill = "void at::native::vectorized_elementwise_kernel<4, at::native::FillFunctor<float> >(int)"
+    copy = "__amd_rocclr_copyBuffer"
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    # the copy of a 1024 KiB buffer reads FETCH_SIZE 512 (factor 2), the fill writes 1024 (factor 1)
+    _write(str(tmp_path / "fetch" / "run_counter_collection.csv"), hdr,
+           [[copy, "FETCH_SIZE", 512], [kname, "FETCH_SIZE", 100], [kname, "FETCH_SIZE", 300]])
+    _write(str(tmp_path / "write" / "run_counter_collection.csv"), hdr,
+           [[fill, "WRITE_SIZE", 1024], [kname, "WRITE_SIZE", 50]])
+    _write(str(tmp_path / "trace" / "run_kernel_stats.csv"), ["Name", "Calls", "AverageNs"],
+           [[kname, 4, 1000.0], [copy, 1, 10.0]])
+    table = bench.ingest_counters(str(tmp_path))
+    d = json.load(open(out))
+    assert d["fetch_factor"] == 2.0 and d["write_factor"] == 1.0 and d["source_sha"] == bench.source_sha()
+    g = d["kernels"]["k_gather"]
+    assert g["calls"] == 4 and g["bytes_per_launch"] == (200 * 2.0 + 50 * 1.0) * 1024.0
+    assert "`k_gather`" in table
+    # counters taken on other kernel sources are not reported
+    assert bench.measured_traffic("k_gather") == g["bytes_per_launch"]
+    d["source_sha"] = "0" * 16
+    json.dump(d, open(out, "w"))
+    assert bench.measured_traffic("k_gather") is None
+
+
+def test_ingestion_needs_the_calibration_runs(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    _write(str(tmp_path / "fetch" / "run_counter_collection.csv"), hdr, [["x", "FETCH_SIZE", 1]])
+    _write(str(tmp_path / "write" / "run_counter_collection.csv"), hdr, [["x", "WRITE_SIZE", 1]])
+    _write(str(tmp_path / "trace" / "run_kernel_stats.csv"), ["Name", "Calls", "AverageNs"], [["x", 1, 1.0]])
+    with pytest.raises(SystemExit):
+        bench.ingest_counters(str(tmp_path))
+    assert not (tmp_path / "traffic.json").exists()
