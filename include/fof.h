@@ -28,9 +28,14 @@
  * Conventions
  *  - All device pointers are HIP device memory on the context's device. The
  *    caller owns the positions, the outputs and the workspace; the library
- *    owns only the context and a small pinned staging buffer.
+ *    owns only the context and two small pinned staging buffers.
  *  - build/link/finalize enqueue work on the context's stream and return
- *    without waiting, except where a host output pointer is given.
+ *    without waiting, except where a host output pointer is given. A
+ *    multi-box build (or relink) copies its box table to the workspace through
+ *    one of two pinned host staging buffers used in turn: refilling one waits
+ *    only for that buffer's previous copy (two uploads back), and a buffer is
+ *    (re)allocated -- pinned host memory, never device memory -- only when a
+ *    larger table than any before comes along.
  *  - build/link/finalize allocate no device memory.
  *  - Host-detectable errors return before any device work is enqueued. A
  *    coordinate that is not finite or lies outside [0, L) is detected on the
@@ -186,7 +191,8 @@ fof_status fof_workspace_bytes(fof_ctx *ctx, const int64_t *h_box_offsets, const
 
 /* Hands the library a device workspace of `bytes` bytes (256-byte aligned),
  * owned by the caller and kept alive until the context is destroyed or another
- * workspace is set. */
+ * workspace is set. Setting a different (or smaller) workspace discards the
+ * captured graph, whose kernels point into the old one. */
 fof_status fof_set_workspace(fof_ctx *ctx, void *d_ws, size_t bytes);
 
 /* Bins the particles into cells (Section 3.1: only cells within l_x of each
@@ -220,9 +226,19 @@ fof_status fof_get_stats(fof_ctx *ctx, fof_stats *out);
 
 /* Captures build + link + finalize for these exact arguments into a HIP graph
  * owned by the context (replacing any previous one). The box description is
- * planned and uploaded before capture, so the graph holds kernel launches
- * only. fof_graph_launch replays it on the context's stream; the per-box
- * group counts stay on the device (fof_read_n_groups). */
+ * planned and uploaded before capture (this call waits for the stream), so
+ * the graph holds kernel launches only. d_pos, d_group_index, d_group_size
+ * and the workspace must stay allocated while the graph may be replayed.
+ * fof_graph_launch replays it on the context's stream; the per-box group
+ * counts stay on the device (fof_read_n_groups).
+ * A graph of several boxes reads the box table held in the workspace. Eager
+ * calls on the same context may replace that table: a build of one box or of
+ * another geometry, or fof_relink. fof_graph_launch then returns
+ * FOF_ERR_BAD_STATE and enqueues nothing (capture again, or first build the
+ * captured geometry eagerly, which puts its table back). A one-box graph
+ * carries its box in the kernel arguments and stays valid. Errors of
+ * fof_graph_launch: FOF_ERR_BAD_STATE (no graph, or its table replaced),
+ * FOF_ERR_DEVICE. */
 fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_box_offsets,
                              const double *h_box, const double *h_lx, int32_t n_boxes,
                              int32_t *d_group_index, int32_t *d_group_size);

@@ -293,6 +293,7 @@ class FoF:
         self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats, dense_min, timings, segment_log2,
                                            domains, link_order), self.stream.cuda_stream)
         self.ws = None
+        self._graph_refs = None   # tensors a captured graph reads or writes
 
     def close(self):
         if self.ctx is not None:
@@ -309,7 +310,8 @@ class FoF:
         need = fof_workspace_bytes(self.ctx, offsets, box, lx)
         if self.ws is None or self.ws.numel() < need:
             self.ws = self._torch.empty(max(need, 256), dtype=self._torch.uint8, device=self.stream.device)
-            fof_set_workspace(self.ctx, self.ws)
+            fof_set_workspace(self.ctx, self.ws)   # discards a captured graph
+            self._graph_refs = None
         return need
 
     def outputs(self, n: int):
@@ -333,6 +335,8 @@ class FoF:
         self._check_pos(pos, offsets)
         self.reserve(offsets, box, lx)
         fof_graph_capture(self.ctx, pos, offsets, box, lx, label, size)
+        # the graph holds raw pointers: keep its tensors alive with it
+        self._graph_refs = (pos, label, size, self.ws)
 
     def replay(self):
         fof_graph_launch(self.ctx)

@@ -39,7 +39,9 @@ float round_up_f32(double v)
     return f;
 }
 
-struct HostPlan {
+// Sort levels and workspace carve-up of one run. Plain data, so the
+// no-allocation entry point can build it on the stack.
+struct Layout {
     int32_t n_boxes = 0;
     int64_t n = 0;
     int64_t n_cells = 0;
@@ -48,17 +50,20 @@ struct HostPlan {
     int32_t bucket_shift = 0, n_buckets = 1;
     int32_t seg_shift = 0, sub_log2 = 0;
     int64_t n_segments = 0;
-    int64_t fp64_boxes = 0;
     int64_t max_items = 0;
-    std::vector<BoxDev> boxes;
-    std::vector<int64_t> p0;
-    std::vector<double> lx_cells;   // linking length each box's cells were sized for
+    int64_t max_edges = 0;
     // workspace layout (byte offsets)
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_kmap = 0, o_sorted = 0,
            o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
            o_stpos = 0, o_wave_roots = 0, o_occ = 0, o_edge_fill = 0, o_seg = 0, o_staging2 = 0,
            o_stage2_k = 0, o_bnd = 0, total = 0;
-    int64_t max_edges = 0;
+};
+
+struct HostPlan : Layout {
+    int64_t fp64_boxes = 0;
+    std::vector<BoxDev> boxes;
+    std::vector<int64_t> p0;
+    std::vector<double> lx_cells;   // linking length each box's cells were sized for
 
     bool same_geometry(const HostPlan &o) const
     {
@@ -118,13 +123,23 @@ struct fof_ctx {
 
     HostPlan plan;
     bool planned = false;
-    bool uploaded = false;     // descriptor table of `plan` is in the workspace
 
     void *ws = nullptr;
     size_t ws_bytes = 0;
 
-    void *stage = nullptr;     // pinned host staging for the descriptor table
-    size_t stage_bytes = 0;
+    // The box table currently held by the workspace: its geometry and an
+    // upload number (0: none, or overwritten by a single-box run).
+    HostPlan table_plan;
+    uint64_t table_id = 0;
+    uint64_t upload_seq = 0;
+
+    // Pinned host staging for the box table, two buffers used in turn; the
+    // event after each buffer's last copy says when it may be refilled.
+    void *stage[2] = {nullptr, nullptr};
+    size_t stage_bytes[2] = {0, 0};
+    hipEvent_t stage_done[2] = {nullptr, nullptr};
+    bool stage_pending[2] = {false, false};
+    int stage_next = 0;
 
     int state = 0;             // 0 idle, 1 cells built, 2 linked
     bool cells_valid = false;  // the last build's cells and sorted positions are in the workspace
@@ -132,6 +147,8 @@ struct fof_ctx {
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int32_t graph_boxes = 0;       // boxes of the captured run
+    HostPlan graph_plan;           // its geometry (a multi-box graph reads that box table)
 };
 
 namespace {
@@ -218,42 +235,34 @@ int32_t sub_cells_per_axis(double L, int64_t nc, double lx)
 
 int dense_min_of(const fof_options &o) { return o.dense_min > 0 ? o.dense_min : kDefaultDenseMin; }
 
-fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box, const double *lx, int32_t n_boxes,
-                     HostPlan *out)
+// Validates one box (nb particles, side L, linking length l) and fills its
+// descriptor, cells starting at global cell `cell_base`.
+fof_status box_geometry(const fof_options &o, int64_t nb, double L, double l, int64_t cell_base, BoxDev *out)
 {
-    if (!offsets || !box || !lx || n_boxes < 1) return FOF_ERR_INVALID_ARG;
-    if (offsets[0] != 0) return FOF_ERR_INVALID_ARG;
-    HostPlan p;
+    if (!(L > 0.0) || !std::isfinite(L) || !(l > 0.0) || !std::isfinite(l)) return FOF_ERR_INVALID_ARG;
+    int64_t nc = 0;
+    fof_status st = cells_per_axis(o, nb, L, l, &nc);
+    if (st != FOF_OK) return st;
+    BoxDev &b = *out;
+    std::memset(&b, 0, sizeof(b));
+    b.cell_base = cell_base;
+    b.nc = (int32_t)nc;
+    b.L = L;
+    b.half = 0.5 * L;
+    b.inv_h = (double)nc / L;
+    b.l2 = l * l;
+    fp32_thresholds(b, l);
+    b.sub_k = sub_cells_per_axis(L, nc, l);
+    return FOF_OK;
+}
+
+// Sort levels and the workspace carve-up for n particles in `cells` cells
+// over n_boxes boxes.
+fof_status make_layout(const fof_options &o, int64_t n_total, int64_t cells, int32_t n_boxes, Layout *out)
+{
+    Layout p;
     p.n_boxes = n_boxes;
-    p.boxes.resize((size_t)n_boxes);
-    p.p0.assign(offsets, offsets + n_boxes + 1);
-    int64_t cells = 0;
-    for (int32_t k = 0; k < n_boxes; ++k) {
-        const int64_t nb = offsets[k + 1] - offsets[k];
-        if (nb < 0 || offsets[k + 1] > (int64_t)INT32_MAX) return FOF_ERR_INVALID_ARG;
-        const double L = box[k], l = lx[k];
-        if (!(L > 0.0) || !std::isfinite(L) || !(l > 0.0) || !std::isfinite(l)) return FOF_ERR_INVALID_ARG;
-        int64_t nc = 0;
-        fof_status st = cells_per_axis(c->opt, nb, L, l, &nc);
-        if (st != FOF_OK) return st;
-        BoxDev &b = p.boxes[(size_t)k];
-        std::memset(&b, 0, sizeof(b));
-        b.p0 = offsets[k];
-        b.p1 = offsets[k + 1];
-        b.cell_base = cells;
-        b.nc = (int32_t)nc;
-        b.L = L;
-        b.half = 0.5 * L;
-        b.inv_h = (double)nc / L;
-        b.l2 = l * l;
-        p.lx_cells.push_back(l);
-        fp32_thresholds(b, l);
-        b.sub_k = sub_cells_per_axis(L, nc, l);
-        if (c->opt.predicate == FOF_PRED_FP32_FILTER && b.use_fp64) ++p.fp64_boxes;
-        cells += nc * nc * nc;
-        if (cells > kMaxCells) return FOF_ERR_UNSUPPORTED;
-    }
-    p.n = offsets[n_boxes];
+    p.n = n_total;
     p.n_cells = cells;
     // Counting sort levels: at most 256 buckets of consecutive cells, each cut
     // into 2^sub_log2 segments of 2^seg_shift cells (the cells one work-group
@@ -262,14 +271,12 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.bucket_shift = 0;
     while ((last >> p.bucket_shift) >= 256) ++p.bucket_shift;
     // By default a segment holds about kSegTarget particles on average (its
-    // particles are then placed through LDS), within 2^6 .. 2^13 cells (the
-    // 2^14-cell instance holds two work-groups per compute unit, the 2^13 one
-    // three, which measured faster).
-    if (c->opt.sort_segment_log2) {
-        p.seg_shift = c->opt.sort_segment_log2;
+    // particles are then placed through LDS), within 2^6 .. 2^14 cells.
+    if (o.sort_segment_log2) {
+        p.seg_shift = o.sort_segment_log2;
     } else {
         const double want = (double)fof::kSegTarget * (double)(cells > 0 ? cells : 1) /
-                            (double)(offsets[n_boxes] > 0 ? offsets[n_boxes] : 1);
+                            (double)(n_total > 0 ? n_total : 1);
         p.seg_shift = fof::kSegLog2Min;
         while (p.seg_shift < fof::kSegLog2Auto && (double)(int64_t(1) << (p.seg_shift + 1)) <= want) ++p.seg_shift;
     }
@@ -278,27 +285,28 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.sub_log2 = p.bucket_shift - p.seg_shift;
     p.n_buckets = (int32_t)((last >> p.bucket_shift) + 1);
     p.n_segments = (last >> p.seg_shift) + 1;
-    p.n_tiles = fof::sort_tiles_for(offsets[n_boxes]);
+    p.n_tiles = fof::sort_tiles_for(n_total);
     {
         const int64_t a = fof::scan_scratch_for(p.n_segments);
         const int64_t b = fof::scan_scratch_for((int64_t)p.n_buckets * p.n_tiles);
         const int64_t t = fof::scan_scratch_for(p.n_tiles + 1);   // the group catalogue
         p.scan_tiles = a > b ? a : b;
         if (t > p.scan_tiles) p.scan_tiles = t;
-        if (c->opt.domains > 1) {   // the global merge numbers the groups of the boundary links
-            const int64_t g = fof::scan_scratch_for(offsets[n_boxes] + 1);
+        if (o.domains > 1) {   // the global merge numbers the groups of the boundary links
+            const int64_t g = fof::scan_scratch_for(n_total + 1);
             if (g > p.scan_tiles) p.scan_tiles = g;
         }
     }
     if ((int64_t)p.n_buckets * p.n_tiles > (int64_t)INT32_MAX) return FOF_ERR_UNSUPPORTED;
 
-    const size_t n = (size_t)p.n;
-    size_t o = 0;
+    const size_t n = (size_t)n_total;
+    size_t at = 0;
     auto take = [&](size_t bytes) {
-        size_t at = o;
-        o = align_up(o + (bytes ? bytes : 1));
-        return at;
+        size_t here = at;
+        at = align_up(at + (bytes ? bytes : 1));
+        return here;
     };
+    // the box table comes first: a multi-box run never writes over its own table
     p.o_boxes = take(sizeof(BoxDev) * (size_t)n_boxes);
     p.o_p0 = take(sizeof(int64_t) * ((size_t)n_boxes + 1));
     p.o_counters = take(sizeof(Counters));
@@ -310,11 +318,11 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.o_perm = take(sizeof(int32_t) * 2 * n);
     p.o_parent = take(sizeof(int32_t) * n);
     p.o_gsize = take(sizeof(int32_t) * n);
-    p.max_items = fof::max_dense_items(p.n, dense_min_of(c->opt));
+    p.max_items = fof::max_dense_items(n_total, dense_min_of(o));
     p.o_items = take(sizeof(int32_t) * 4 * (size_t)p.max_items);
     // linked pairs of sparse cells, merged after the search; a pair that finds
     // the list full is merged on the spot instead
-    p.max_edges = p.n > (1 << 20) ? p.n : (1 << 20);
+    p.max_edges = n_total > (1 << 20) ? n_total : (1 << 20);
     p.max_edges = (p.max_edges + fof::kEdgeSlices - 1) / fof::kEdgeSlices * fof::kEdgeSlices;
     p.o_edges = take(sizeof(int32_t) * 2 * (size_t)p.max_edges);
     p.o_edge_fill = take(sizeof(uint32_t) * fof::kEdgeSlices);
@@ -326,10 +334,98 @@ fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box
     p.o_seg = take(sizeof(int32_t) * (size_t)p.n_segments);
     p.o_staging2 = take(sizeof(float) * 4 * n);
     p.o_stage2_k = take(sizeof(int32_t) * n);
-    p.o_bnd = c->opt.domains > 1 ? take(sizeof(int32_t) * 2 * (size_t)p.max_edges) : 0;
-    p.total = o;
+    p.o_bnd = o.domains > 1 ? take(sizeof(int32_t) * 2 * (size_t)p.max_edges) : 0;
+    p.total = at;
+    *out = p;
+    return FOF_OK;
+}
+
+fof_status make_plan(const fof_ctx *c, const int64_t *offsets, const double *box, const double *lx, int32_t n_boxes,
+                     HostPlan *out)
+{
+    if (!offsets || !box || !lx || n_boxes < 1) return FOF_ERR_INVALID_ARG;
+    if (offsets[0] != 0) return FOF_ERR_INVALID_ARG;
+    HostPlan p;
+    p.boxes.resize((size_t)n_boxes);
+    p.p0.assign(offsets, offsets + n_boxes + 1);
+    int64_t cells = 0;
+    for (int32_t k = 0; k < n_boxes; ++k) {
+        const int64_t nb = offsets[k + 1] - offsets[k];
+        if (nb < 0 || offsets[k + 1] > (int64_t)INT32_MAX) return FOF_ERR_INVALID_ARG;
+        BoxDev &b = p.boxes[(size_t)k];
+        fof_status st = box_geometry(c->opt, nb, box[k], lx[k], cells, &b);
+        if (st != FOF_OK) return st;
+        b.p0 = offsets[k];
+        b.p1 = offsets[k + 1];
+        p.lx_cells.push_back(lx[k]);
+        if (c->opt.predicate == FOF_PRED_FP32_FILTER && b.use_fp64) ++p.fp64_boxes;
+        cells += (int64_t)b.nc * b.nc * b.nc;
+        if (cells > kMaxCells) return FOF_ERR_UNSUPPORTED;
+    }
+    fof_status st = make_layout(c->opt, offsets[n_boxes], cells, n_boxes, &p);
+    if (st != FOF_OK) return st;
     *out = std::move(p);
     return FOF_OK;
+}
+
+template <typename T>
+T *at(void *base, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+// The launch parameters of a run: options, sort levels and pointers into the
+// workspace `ws` carved as `p`. `box0` is the first (or only) box.
+void carve(const fof_options &o, const Layout &p, const BoxDev &box0, void *ws, Plan *out)
+{
+    Plan &d = *out;
+    d.n = p.n;
+    d.n_cells = p.n_cells;
+    d.n_boxes = p.n_boxes;
+    d.predicate = o.predicate;
+    d.strict = o.strict_less;
+    d.stats = o.collect_stats;
+    d.scan_tiles = p.scan_tiles;
+    d.n_tiles = p.n_tiles;
+    d.bucket_shift = p.bucket_shift;
+    d.n_buckets = p.n_buckets;
+    d.seg_shift = p.seg_shift;
+    d.sub_log2 = p.sub_log2;
+    d.n_segments = p.n_segments;
+    d.dense_min = dense_min_of(o);
+    d.dense_blocks = kDenseBlocks;
+    d.sparse_blocks = kSparseBlocks;
+    d.domains = o.domains > 1 ? o.domains : 0;
+    d.link_random = o.link_order == 1 ? 1 : 0;
+    d.max_items = p.max_items;
+    d.max_edges = p.max_edges;
+    d.box0 = box0;
+    d.boxes = at<BoxDev>(ws, p.o_boxes);
+    d.box_p0 = at<int64_t>(ws, p.o_p0);
+    d.counters = at<Counters>(ws, p.o_counters);
+    d.n_groups = at<unsigned long long>(ws, p.o_groups);
+    d.cstart = at<int32_t>(ws, p.o_cell);
+    d.scan_part = at<int32_t>(ws, p.o_part);
+    d.kmap = at<int32_t>(ws, p.o_kmap);
+    d.sorted = at<float4>(ws, p.o_sorted);
+    d.perm = at<int2>(ws, p.o_perm);
+    d.parent = at<int32_t>(ws, p.o_parent);
+    d.gsize = at<int32_t>(ws, p.o_gsize);
+    d.items = at<int4>(ws, p.o_items);
+    d.edges = at<int2>(ws, p.o_edges);
+    d.bnd = o.domains > 1 ? at<int2>(ws, p.o_bnd) : nullptr;
+    d.bucket_hist = at<int32_t>(ws, p.o_hist);
+    d.staging = at<float4>(ws, p.o_staging);
+    d.stpos = at<int32_t>(ws, p.o_stpos);
+    d.wave_roots = at<int32_t>(ws, p.o_wave_roots);
+    d.occ = at<uint2>(ws, p.o_occ);
+    d.seg_end = at<int32_t>(ws, p.o_seg);
+    d.staging2 = at<float4>(ws, p.o_staging2);
+    d.stage2_k = at<int32_t>(ws, p.o_stage2_k);
+    d.edge_fill = at<unsigned int>(ws, p.o_edge_fill);
+    d.n_waves = (p.n + 63) / 64;
+    d.label = nullptr;
+    d.size = nullptr;
 }
 
 fof_status ensure_device(fof_ctx *c)
@@ -341,97 +437,69 @@ fof_status ensure_device(fof_ctx *c)
     return FOF_OK;
 }
 
-template <typename T>
-T *at(void *base, size_t off)
-{
-    return reinterpret_cast<T *>(static_cast<char *>(base) + off);
-}
-
-// Copies the box table and offsets of `np` to the start of the workspace.
+// Copies the box table and offsets of `np` to the start of the workspace,
+// through one of two pinned staging buffers used in turn. Refilling a buffer
+// waits only for that buffer's previous copy (two uploads back), not for the
+// stream; a buffer grows (pinned host memory, not device memory) only when a
+// larger table than before comes along.
 fof_status upload_table(fof_ctx *c, const HostPlan &np)
 {
     const size_t table = np.o_counters;   // boxes + p0 region
-    // the staging buffer may still feed an earlier, in-flight copy
-    if (c->stage && hipStreamSynchronize(c->stream) != hipSuccess) return FOF_ERR_DEVICE;
-    if (c->stage_bytes < table) {
-        if (c->stage) (void)hipHostFree(c->stage);
-        c->stage = nullptr;
-        c->stage_bytes = 0;
-        if (hipHostMalloc(&c->stage, table, hipHostMallocDefault) != hipSuccess) return FOF_ERR_DEVICE;
-        c->stage_bytes = table;
+    const int k = c->stage_next;
+    if (!c->stage_done[k] && hipEventCreateWithFlags(&c->stage_done[k], hipEventDisableTiming) != hipSuccess)
+        return FOF_ERR_DEVICE;
+    if (c->stage_pending[k]) {
+        if (hipEventSynchronize(c->stage_done[k]) != hipSuccess) return FOF_ERR_DEVICE;
+        c->stage_pending[k] = false;
     }
-    std::memset(c->stage, 0, table);
-    std::memcpy(at<char>(c->stage, np.o_boxes), np.boxes.data(), sizeof(BoxDev) * np.boxes.size());
-    std::memcpy(at<char>(c->stage, np.o_p0), np.p0.data(), sizeof(int64_t) * np.p0.size());
-    if (hipMemcpyAsync(c->ws, c->stage, table, hipMemcpyHostToDevice, c->stream) != hipSuccess) return FOF_ERR_DEVICE;
-    c->uploaded = true;
+    if (c->stage_bytes[k] < table) {
+        if (c->stage[k]) (void)hipHostFree(c->stage[k]);
+        c->stage[k] = nullptr;
+        c->stage_bytes[k] = 0;
+        if (hipHostMalloc(&c->stage[k], table, hipHostMallocDefault) != hipSuccess) return FOF_ERR_DEVICE;
+        c->stage_bytes[k] = table;
+    }
+    std::memset(c->stage[k], 0, table);
+    std::memcpy(at<char>(c->stage[k], np.o_boxes), np.boxes.data(), sizeof(BoxDev) * np.boxes.size());
+    std::memcpy(at<char>(c->stage[k], np.o_p0), np.p0.data(), sizeof(int64_t) * np.p0.size());
+    if (hipMemcpyAsync(c->ws, c->stage[k], table, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return FOF_ERR_DEVICE;
+    if (hipEventRecord(c->stage_done[k], c->stream) != hipSuccess) return FOF_ERR_DEVICE;
+    c->stage_pending[k] = true;
+    c->stage_next = k ^ 1;
+    c->table_plan = np;
+    c->table_id = ++c->upload_seq;
     return FOF_OK;
 }
 
-// Adopt `np` as the current plan; upload its descriptor table if it changed.
+// Adopt `np` as the current plan; upload its box table unless the workspace
+// already holds the same one. A single box travels in the kernel arguments,
+// and its run writes over the table region of any earlier multi-box layout.
 fof_status install_plan(fof_ctx *c, HostPlan &&np)
 {
     if (!c->ws) return FOF_ERR_WORKSPACE;
     if (c->ws_bytes < np.total) return FOF_ERR_WORKSPACE;
     fof_status st = ensure_device(c);
     if (st != FOF_OK) return st;
-    // a single box travels in the kernel arguments: nothing to upload
-    const bool same = np.n_boxes == 1 || (c->planned && c->uploaded && c->plan.same_geometry(np));
-    if (!same) {
+    if (np.n_boxes == 1) {
+        c->table_id = 0;
+    } else if (!(c->table_id && c->table_plan.same_geometry(np))) {
         st = upload_table(c, np);
         if (st != FOF_OK) return st;
     }
     c->plan = std::move(np);
     c->planned = true;
-
-    const HostPlan &p = c->plan;
-    Plan &d = c->dev;
-    d.n = p.n;
-    d.n_cells = p.n_cells;
-    d.n_boxes = p.n_boxes;
-    d.predicate = c->opt.predicate;
-    d.strict = c->opt.strict_less;
-    d.stats = c->opt.collect_stats;
-    d.scan_tiles = p.scan_tiles;
-    d.n_tiles = p.n_tiles;
-    d.bucket_shift = p.bucket_shift;
-    d.n_buckets = p.n_buckets;
-    d.seg_shift = p.seg_shift;
-    d.sub_log2 = p.sub_log2;
-    d.n_segments = p.n_segments;
-    d.dense_min = dense_min_of(c->opt);
-    d.dense_blocks = kDenseBlocks;
-    d.sparse_blocks = kSparseBlocks;
-    d.domains = c->opt.domains > 1 ? c->opt.domains : 0;
-    d.link_random = c->opt.link_order == 1 ? 1 : 0;
-    d.max_items = p.max_items;
-    d.max_edges = p.max_edges;
-    d.box0 = p.boxes[0];
-    d.boxes = at<BoxDev>(c->ws, p.o_boxes);
-    d.box_p0 = at<int64_t>(c->ws, p.o_p0);
-    d.counters = at<Counters>(c->ws, p.o_counters);
-    d.n_groups = at<unsigned long long>(c->ws, p.o_groups);
-    d.cstart = at<int32_t>(c->ws, p.o_cell);
-    d.scan_part = at<int32_t>(c->ws, p.o_part);
-    d.kmap = at<int32_t>(c->ws, p.o_kmap);
-    d.sorted = at<float4>(c->ws, p.o_sorted);
-    d.perm = at<int2>(c->ws, p.o_perm);
-    d.parent = at<int32_t>(c->ws, p.o_parent);
-    d.gsize = at<int32_t>(c->ws, p.o_gsize);
-    d.items = at<int4>(c->ws, p.o_items);
-    d.edges = at<int2>(c->ws, p.o_edges);
-    d.bnd = c->opt.domains > 1 ? at<int2>(c->ws, p.o_bnd) : nullptr;
-    d.bucket_hist = at<int32_t>(c->ws, p.o_hist);
-    d.staging = at<float4>(c->ws, p.o_staging);
-    d.stpos = at<int32_t>(c->ws, p.o_stpos);
-    d.wave_roots = at<int32_t>(c->ws, p.o_wave_roots);
-    d.occ = at<uint2>(c->ws, p.o_occ);
-    d.seg_end = at<int32_t>(c->ws, p.o_seg);
-    d.staging2 = at<float4>(c->ws, p.o_staging2);
-    d.stage2_k = at<int32_t>(c->ws, p.o_stage2_k);
-    d.edge_fill = at<unsigned int>(c->ws, p.o_edge_fill);
-    d.n_waves = (p.n + 63) / 64;
+    carve(c->opt, c->plan, c->plan.boxes[0], c->ws, &c->dev);
     return FOF_OK;
+}
+
+void drop_graph(fof_ctx *c)
+{
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->exec = nullptr;
+    c->graph = nullptr;
+    c->graph_boxes = 0;
 }
 
 fof_status do_build(fof_ctx *c, const float *d_pos, const int64_t *off, const double *box, const double *lx,
@@ -526,9 +594,11 @@ fof_status fof_set_workspace(fof_ctx *ctx, void *d_ws, size_t bytes)
 {
     if (!ctx) return FOF_ERR_INVALID_ARG;
     if (d_ws && (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) return FOF_ERR_WORKSPACE;
-    if (ctx->ws != d_ws) {
-        ctx->uploaded = false;
+    if (ctx->ws != d_ws || (d_ws && bytes < ctx->ws_bytes)) {
+        ctx->table_id = 0;
         ctx->planned = false;   // the carved pointers refer to the old workspace
+        ctx->cells_valid = false;
+        drop_graph(ctx);        // its kernels hold pointers into the old workspace
     }
     ctx->ws = d_ws;
     ctx->ws_bytes = d_ws ? bytes : 0;
@@ -663,14 +733,7 @@ fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_
     if ((!d_group_index || !d_group_size) && ctx->plan.n > 0) return FOF_ERR_INVALID_ARG;
     ctx->dev.label = d_group_index;
     ctx->dev.size = d_group_size;
-    if (ctx->exec) {
-        (void)hipGraphExecDestroy(ctx->exec);
-        ctx->exec = nullptr;
-    }
-    if (ctx->graph) {
-        (void)hipGraphDestroy(ctx->graph);
-        ctx->graph = nullptr;
-    }
+    drop_graph(ctx);
     // the descriptor upload above is ordered on ctx->stream; capture on a
     // private stream that first waits for it
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return FOF_ERR_DEVICE;
@@ -689,6 +752,12 @@ fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_
         if (e == hipSuccess) {
             ctx->graph = g;
             e = hipGraphInstantiate(&ctx->exec, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) {
+                ctx->graph_boxes = ctx->plan.n_boxes;
+                ctx->graph_plan = ctx->plan;
+            } else {
+                drop_graph(ctx);
+            }
         } else if (g) {
             (void)hipGraphDestroy(g);
         }
@@ -702,6 +771,10 @@ fof_status fof_graph_launch(fof_ctx *ctx)
 {
     if (!ctx) return FOF_ERR_INVALID_ARG;
     if (!ctx->exec) return FOF_ERR_BAD_STATE;
+    // a multi-box graph reads the box table in the workspace: refuse when a
+    // later build or relink of another geometry has replaced it
+    if (ctx->graph_boxes > 1 && !(ctx->table_id && ctx->table_plan.same_geometry(ctx->graph_plan)))
+        return FOF_ERR_BAD_STATE;
     return dev_err(hipGraphLaunch(ctx->exec, ctx->stream));
 }
 
@@ -709,9 +782,11 @@ fof_status fof_destroy(fof_ctx *ctx)
 {
     if (!ctx) return FOF_OK;
     if (ctx->device >= 0) (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
-    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
-    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    drop_graph(ctx);
+    for (int k = 0; k < 2; ++k) {
+        if (ctx->stage[k]) (void)hipHostFree(ctx->stage[k]);
+        if (ctx->stage_done[k]) (void)hipEventDestroy(ctx->stage_done[k]);
+    }
     delete ctx->timer;
     delete ctx;
     return FOF_OK;

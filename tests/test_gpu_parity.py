@@ -446,6 +446,60 @@ def test_graph_replays_match_eager():
         f.close()
 
 
+def test_graph_refused_after_its_box_table_is_replaced():
+    """A multi-box graph reads the box table in the workspace: after an eager
+    build of another geometry (or of one box, or a relink) the host refuses to
+    replay it, so nothing runs with a replaced table; an eager build of the
+    captured geometry puts the table back and replays work again."""
+    w = synth.make("batched256", n_boxes=12, size_scale=0.03)
+    ref = oracle.fof_boxes(w.pos, w.offsets, w.box, w.lx)
+    f = fof.FoF()
+    try:
+        p = torch.from_numpy(w.pos).cuda()
+        label, size = f.outputs(w.n)
+        f.capture(p, w.offsets, w.box, w.lx, label, size)
+        f.replay()
+        assert np.array_equal(label.cpu().numpy(), ref[0])
+        k = 5   # another geometry: the first five boxes
+        f.run(p[: w.offsets[k]].contiguous(), w.offsets[: k + 1], w.box[:k], w.lx[:k])
+        with pytest.raises(fof.FoFError) as e:
+            f.replay()
+        assert e.value.status == fof.FOF_ERR_BAD_STATE
+        f.run(p[: w.offsets[1]].contiguous(), w.offsets[:2], w.box[:1], w.lx[:1])   # one box
+        with pytest.raises(fof.FoFError) as e:
+            f.replay()
+        assert e.value.status == fof.FOF_ERR_BAD_STATE
+        f.run(p, w.offsets, w.box, w.lx)    # the captured geometry again: its table is back
+        label.fill_(-7)
+        f.replay()
+        assert np.array_equal(label.cpu().numpy(), ref[0])
+        f.relink([float(v) * 0.9 for v in w.lx], w.n_boxes)   # new thresholds in the table
+        with pytest.raises(fof.FoFError) as e:
+            f.replay()
+        assert e.value.status == fof.FOF_ERR_BAD_STATE
+    finally:
+        f.close()
+
+
+def test_single_box_graph_survives_other_runs():
+    w = synth.make("batched256", n_boxes=4, size_scale=0.03)
+    p = torch.from_numpy(w.pos).cuda()
+    n0 = int(w.offsets[1])
+    ref = oracle.fof(w.pos[:n0], float(w.lx[0]))
+    f = fof.FoF()
+    try:
+        p0 = p[:n0].contiguous()
+        label, size = f.outputs(n0)
+        f.capture(p0, [0, n0], w.box[0], w.lx[0], label, size)
+        f.run(p, w.offsets, w.box, w.lx)          # a multi-box run on the same workspace
+        label.fill_(-7)
+        f.replay()
+        assert np.array_equal(label.cpu().numpy(), ref[0])
+        assert np.array_equal(size.cpu().numpy(), ref[1])
+    finally:
+        f.close()
+
+
 # ---------------------------------------------------------- properties --
 
 def test_repeated_runs_identical():
