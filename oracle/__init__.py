@@ -53,6 +53,9 @@ def _load():
     lib.oracle_fof_boxes.argtypes = [ctypes.c_int32, i64p, f32p, f64p, f64p, ctypes.c_int, i32p, i32p, i64p,
                                      ctypes.c_int]
     lib.oracle_fof_boxes.restype = ctypes.c_int
+    lib.oracle_fof_parallel.argtypes = [ctypes.c_int64, f32p, ctypes.c_double, ctypes.c_double, ctypes.c_int, i32p,
+                                        i32p, i64p, ctypes.c_int]
+    lib.oracle_fof_parallel.restype = ctypes.c_int
     lib.oracle_cells_per_axis.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double]
     lib.oracle_cells_per_axis.restype = ctypes.c_int64
     lib.oracle_component.argtypes = [ctypes.c_int64, f32p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -98,6 +101,20 @@ def fof(pos, lx: float, box: float = 1.0, strict: bool = False, brute: bool = Fa
     fn = _load().oracle_fof_brute if brute else _load().oracle_fof
     _check(fn(n, _p(p, ctypes.c_float), float(box), float(lx), int(strict), _p(label, ctypes.c_int32),
               _p(size, ctypes.c_int32), ctypes.byref(ng)))
+    return label, size, int(ng.value)
+
+
+def fof_parallel(pos, lx: float, box: float = 1.0, strict: bool = False, threads: int = 1):
+    """The same outputs as fof(), with the link search over host threads (for
+    inputs of up to ~10^9 particles)."""
+    p = _pos(pos)
+    n = len(p)
+    label = np.empty(n, dtype=np.int32)
+    size = np.empty(n, dtype=np.int32)
+    ng = ctypes.c_int64(0)
+    _check(_load().oracle_fof_parallel(n, _p(p, ctypes.c_float), float(box), float(lx), int(strict),
+                                       _p(label, ctypes.c_int32), _p(size, ctypes.c_int32), ctypes.byref(ng),
+                                       int(threads)))
     return label, size, int(ng.value)
 
 

@@ -379,3 +379,170 @@ int oracle_components_of(int64_t n, const float *pos, double L, double lx, int s
     free(queue);
     return ORACLE_OK;
 }
+
+/* ------------------------------------- the same result over host threads -- */
+
+/* A growing list of linked pairs (slot pairs, see below). */
+typedef struct {
+    int32_t *pair;
+    int64_t count, cap;
+} link_list;
+
+static int link_push(link_list *l, int32_t a, int32_t b)
+{
+    if (l->count == l->cap) {
+        int64_t cap = l->cap ? 2 * l->cap : 4096;
+        int32_t *p = (int32_t *)realloc(l->pair, sizeof(int32_t) * 2 * (size_t)cap);
+        if (!p) return ORACLE_ERR_MEM;
+        l->pair = p;
+        l->cap = cap;
+    }
+    l->pair[2 * l->count] = a;
+    l->pair[2 * l->count + 1] = b;
+    l->count += 1;
+    return ORACLE_OK;
+}
+
+/* oracle_fof for inputs of up to ~10^9 particles, where one thread would take
+ * hours: the same graph, the same components and the same outputs, with the
+ * distance tests spread over `threads` host threads. The steps:
+ *  1. cells of side L/n_c >= l_x (1 + 2^-20), as many per axis as fit but
+ *     at most 1290 (n_c^3 < 2^31): finer than oracle_fof's, which are capped
+ *     at about one particle per cell, since here the slots make empty cells
+ *     cheap; brute force (through oracle_fof) when fewer than 3 fit;
+ *  2. the particles grouped by cell into "slots": the particle count of every
+ *     cell, a prefix sum over the cells, and each particle takes the next
+ *     free slot of its cell (their order inside a cell is arbitrary). Only
+ *     memory locality differs from the head/next list: the slots of a cell
+ *     are contiguous;
+ *  3. for every particle i, every particle j of the 27 cells of its periodic
+ *     shell with input index j > i is tested with the canonical predicate
+ *     (each unordered pair once); the cells of each z-plane are searched by
+ *     one thread, which keeps that plane's linked pairs, as slot pairs, in a
+ *     list of its own;
+ *  4. union-find over the slot pairs, one thread, plane by plane (union by the
+ *     smaller root, full path compression, as in oracle_fof);
+ *  5. outputs: label = the smallest input index of the component, size at the
+ *     particle with that index, the number of components.
+ * The link set is the graph's edge set whatever the order inside cells and
+ * the thread count, and the outputs depend only on its components. */
+int oracle_fof_parallel(int64_t n, const float *pos, double L, double lx, int strict,
+                        int32_t *label, int32_t *size, int64_t *n_groups, int threads)
+{
+    int st = validate(n, pos, L, lx);
+    if (st) return st;
+    const double fit = floor(L / (lx * (1.0 + 1.0 / 1048576.0)));
+    if (!(fit >= 3.0) || n == 0) return oracle_fof(n, pos, L, lx, strict, label, size, n_groups);
+    const int64_t nc = fit < 1290.0 ? (int64_t)fit : 1290;
+    const int nt = threads > 0 ? threads : 1;
+    const int64_t ncell = nc * nc * nc;
+    int32_t *cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    uint32_t *first = (uint32_t *)calloc((size_t)ncell + 1, sizeof(uint32_t));
+    float *spos = (float *)malloc(sizeof(float) * 3 * (size_t)n);
+    int32_t *orig = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *parent = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    link_list *lists = (link_list *)calloc((size_t)nc, sizeof(link_list));
+    if (!cell || !first || !spos || !orig || !parent || !lists) {
+        free(cell); free(first); free(spos); free(orig); free(parent); free(lists);
+        return ORACLE_ERR_MEM;
+    }
+
+    /* 2. cells, counts, prefix sum, slots */
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = (cell_of(pos[3 * i + 2], nc, L) * nc + cell_of(pos[3 * i + 1], nc, L)) * nc +
+                    cell_of(pos[3 * i + 0], nc, L);
+        cell[i] = (int32_t)c;
+        __atomic_fetch_add(&first[c + 1], 1u, __ATOMIC_RELAXED);
+    }
+    for (int64_t c = 0; c < ncell; ++c) first[c + 1] += first[c];
+    /* first[c] is the next free slot of cell c; afterwards it is the end of c */
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t s = __atomic_fetch_add(&first[cell[i]], 1u, __ATOMIC_RELAXED);
+        spos[3 * (int64_t)s + 0] = pos[3 * i + 0];
+        spos[3 * (int64_t)s + 1] = pos[3 * i + 1];
+        spos[3 * (int64_t)s + 2] = pos[3 * i + 2];
+        orig[s] = (int32_t)i;
+    }
+    memmove(first + 1, first, sizeof(uint32_t) * (size_t)ncell);
+    first[0] = 0; /* cell c: slots first[c] .. first[c+1]-1 */
+
+    /* 3. link search, one z-plane of cells per task */
+    const double l2 = lx * lx;
+    int status = ORACLE_OK;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+    for (int64_t cz = 0; cz < nc; ++cz) {
+        link_list *out = &lists[cz];
+        int bad = 0;
+        for (int64_t cy = 0; cy < nc && !bad; ++cy)
+            for (int64_t cx = 0; cx < nc && !bad; ++cx) {
+                const int64_t c = (cz * nc + cy) * nc + cx;
+                if (first[c] == first[c + 1]) continue;
+                /* the slots of the 27 cells of the periodic shell */
+                uint32_t lo[27], hi[27];
+                int k = 0;
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx, ++k) {
+                            int64_t ox = cx + dx, oy = cy + dy, oz = cz + dz;
+                            ox += ox < 0 ? nc : (ox >= nc ? -nc : 0);
+                            oy += oy < 0 ? nc : (oy >= nc ? -nc : 0);
+                            oz += oz < 0 ? nc : (oz >= nc ? -nc : 0);
+                            const int64_t o = (oz * nc + oy) * nc + ox;
+                            lo[k] = first[o];
+                            hi[k] = first[o + 1];
+                        }
+                for (uint32_t s = first[c]; s < first[c + 1] && !bad; ++s)
+                    for (k = 0; k < 27; ++k)
+                        for (uint32_t t = lo[k]; t < hi[k]; ++t)
+                            if (orig[t] > orig[s] &&
+                                linked(spos + 3 * (int64_t)s, spos + 3 * (int64_t)t, L, l2, strict))
+                                if (link_push(out, (int32_t)s, (int32_t)t)) bad = 1;
+            }
+        if (bad) {
+#pragma omp critical
+            status = ORACLE_ERR_MEM;
+        }
+    }
+
+    /* 4. union-find over slots */
+    if (status == ORACLE_OK) {
+        for (int64_t s = 0; s < n; ++s) parent[s] = (int32_t)s;
+        for (int64_t cz = 0; cz < nc; ++cz)
+            for (int64_t k = 0; k < lists[cz].count; ++k)
+                unite(parent, lists[cz].pair[2 * k], lists[cz].pair[2 * k + 1]);
+    }
+    for (int64_t cz = 0; cz < nc; ++cz) free(lists[cz].pair);
+    free(lists);
+    free(spos);
+    free(first);
+
+    /* 5. outputs: root of every slot (paths fully compressed by the first
+     * pass), smallest input index and member count per root */
+    int32_t *count = status == ORACLE_OK ? (int32_t *)calloc((size_t)n, sizeof(int32_t)) : NULL;
+    if (status == ORACLE_OK && !count) status = ORACLE_ERR_MEM;
+    if (status == ORACLE_OK) {
+        int32_t *low = cell; /* reused: smallest input index at each root */
+        int64_t groups = 0;
+        for (int64_t s = 0; s < n; ++s) low[s] = INT32_MAX;
+        for (int64_t s = 0; s < n; ++s) {
+            int32_t r = find_root(parent, (int32_t)s);
+            if (orig[s] < low[r]) low[r] = orig[s];
+            count[r] += 1;
+        }
+#pragma omp parallel for schedule(static) num_threads(nt) reduction(+ : groups)
+        for (int64_t s = 0; s < n; ++s) {
+            const int32_t r = parent[s];
+            label[orig[s]] = low[r];
+            size[orig[s]] = orig[s] == low[r] ? count[r] : 0;
+            if (r == s) groups += 1;
+        }
+        *n_groups = groups;
+    }
+    free(count);
+    free(cell);
+    free(orig);
+    free(parent);
+    return status;
+}

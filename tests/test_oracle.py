@@ -12,6 +12,11 @@
   unchanged; labels are the group minima; sizes count the members;
 - statistics: Poisson expectations for i.i.d. uniform points;
 - planted mistakes: mutated copies of the oracle must fail at least one pin.
+
+The threaded variant (oracle_fof_parallel, for the full-size parity checks)
+has pins of its own: the hand fixture, lattices, the tie lattice, brute force,
+scipy's periodic k-d tree, and planted mistakes in its own code (slot
+grouping, shell enumeration, the label and size at the group minimum).
 """
 from __future__ import annotations
 
@@ -247,6 +252,49 @@ def test_components_of_match_union_find():
         assert np.array_equal(np.flatnonzero(mark == first), np.flatnonzero(label == label[s]))
 
 
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_threaded_oracle_equals_sequential(threads):
+    cases = []
+    for b in (0.2, 0.5, 0.9):
+        n = 40000
+        cases.append((synth.clustered(n, 300 + int(10 * b), 0, 0.6), synth.linking_length(b, n), 1.0))
+    n = 20000
+    cases.append((synth.uniform(n, 77), synth.linking_length(0.8, n), 1.0))
+    p = synth.clustered(n, 78, 0, 0.6).astype(np.float64) * 2.5
+    cases.append((np.ascontiguousarray(np.mod(p, 2.5).astype(np.float32)), 2.5 * synth.linking_length(0.6, n), 2.5))
+    for pos, lx, box in cases:
+        for strict in (False, True):
+            ref = oracle.fof(pos, lx, box, strict=strict)
+            got = oracle.fof_parallel(pos, lx, box, strict=strict, threads=threads)
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2]
+
+
+def test_threaded_oracle_tie_lattice_chains_and_edges():
+    pos = lattice(64, seed=1)
+    assert oracle.fof_parallel(pos, 2.0 ** -6, threads=4)[2] == 1
+    assert oracle.fof_parallel(pos, 2.0 ** -6, strict=True, threads=4)[2] == 64 ** 3
+    for axis in range(3):
+        pos = chain_across_boundary(50, 0.01, axis)
+        label, size, ng = oracle.fof_parallel(pos, 0.0101, threads=2)
+        assert ng == 1 and size[0] == 50
+    assert oracle.fof_parallel(np.zeros((0, 3), np.float32), 0.1, threads=2)[2] == 0
+    label, size, ng = oracle.fof_parallel(np.array([[0.3, 0.3, 0.3]], np.float32), 0.1, threads=2)
+    assert ng == 1 and label[0] == 0 and size[0] == 1
+    with pytest.raises(oracle.OracleError):
+        oracle.fof_parallel(np.array([[1.0, 0.3, 0.3]], np.float32), 0.1, threads=2)
+
+
+def test_threaded_oracle_equals_brute_force():
+    for seed in range(4):
+        n = 2048
+        pos = synth.clustered(n, 400 + seed, 0, 0.6)
+        for b in (0.5, 1.5):
+            lx = synth.linking_length(b, n)
+            got = oracle.fof_parallel(pos, lx, threads=4)
+            ref = oracle.fof(pos, lx, brute=True)
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2]
+
+
 def test_boxes_equal_single_box_runs():
     w = synth.make("batched256", n_boxes=6, size_scale=0.02)
     lab1, size1, ng1 = oracle.fof_boxes(w.pos, w.offsets, w.box, w.lx, threads=1)
@@ -299,56 +347,79 @@ MUTANTS = {
 }
 
 
-def _mutant_lib(name, tmp):
+def _mutant_lib(name, tmp, table=None):
     src = open(os.path.join(os.path.dirname(oracle.__file__), "fof_oracle.c")).read()
-    old, new = MUTANTS[name]
+    old, new = (table or MUTANTS)[name]
     assert src.count(old) >= 1, name
     src = src.replace(old, new)
     c = os.path.join(tmp, name + ".c")
     so = os.path.join(tmp, name + ".so")
     open(c, "w").write(src)
-    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", so, c, "-lm"], check=True)
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-o", so, c, "-lm"],
+                   check=True)
     return ctypes.CDLL(so)
 
 
-def _run(lib, pos, lx, box=1.0, strict=False, brute=False):
+# Mistakes in the threaded variant's own code (its slots, shell, outputs).
+PARALLEL_MUTANTS = {
+    "par_own_cell_only": ("for (k = 0; k < 27; ++k)\n", "for (k = 13; k < 14; ++k)\n"),
+    "par_label_root_slot": ("label[orig[s]] = low[r];", "label[orig[s]] = orig[r];"),
+    "par_size_at_root_slot": ("size[orig[s]] = orig[s] == low[r] ? count[r] : 0;",
+                              "size[orig[s]] = r == s ? count[r] : 0;"),
+    "par_no_x_wrap": ("ox += ox < 0 ? nc : (ox >= nc ? -nc : 0);", "ox += ox < 0 ? 1 : (ox >= nc ? -1 : 0);"),
+    "par_cell_ends_as_starts": ("    memmove(first + 1, first, sizeof(uint32_t) * (size_t)ncell);\n", "\n"),
+    "par_skip_last_cell_slot": ("for (uint32_t t = lo[k]; t < hi[k]; ++t)", "for (uint32_t t = lo[k]; t + 1 < hi[k]; ++t)"),
+}
+
+
+def _run(lib, pos, lx, box=1.0, strict=False, brute=False, parallel=False):
     pos = np.ascontiguousarray(pos, dtype=np.float32)
     n = len(pos)
     label = np.empty(n, np.int32)
     size = np.empty(n, np.int32)
     ng = ctypes.c_int64()
-    fn = lib.oracle_fof_brute if brute else lib.oracle_fof
-    fn.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-    st = fn(n, pos.ctypes.data, box, lx, int(strict), label.ctypes.data, size.ctypes.data, ctypes.byref(ng))
+    args = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    if parallel:
+        fn = lib.oracle_fof_parallel
+        fn.argtypes = args + [ctypes.c_int]
+        st = fn(n, pos.ctypes.data, box, lx, int(strict), label.ctypes.data, size.ctypes.data, ctypes.byref(ng), 3)
+    else:
+        fn = lib.oracle_fof_brute if brute else lib.oracle_fof
+        fn.argtypes = args
+        st = fn(n, pos.ctypes.data, box, lx, int(strict), label.ctypes.data, size.ctypes.data, ctypes.byref(ng))
     assert st == 0
     return label, size, ng.value
 
 
-def _pins_pass(lib) -> bool:
-    """The pin battery above, run against an arbitrary oracle library."""
+def _pins_pass(lib, parallel=False) -> bool:
+    """The pin battery above, run against an arbitrary oracle library (its
+    sequential or its threaded function)."""
     try:
         fx = load_fixture("fig2_indirect_u.txt")
         for strict, tag in ((False, "le"), (True, "lt")):
             for brute in (False, True):
-                l, s, g = _run(lib, fx["pos"], fx["lx"], fx["box"], strict, brute)
+                l, s, g = _run(lib, fx["pos"], fx["lx"], fx["box"], strict, brute and not parallel, parallel)
                 if not (np.array_equal(l, fx["labels_" + tag]) and np.array_equal(s, fx["sizes_" + tag])):
                     return False
-        l, s, g = _run(lib, clump_and_pair(), 0.1)
+        l, s, g = _run(lib, clump_and_pair(), 0.1, parallel=parallel)
         if g != 2 or l[1500] != 3:
             return False
         pos = lattice(16, seed=3)
-        if _run(lib, pos, (1 - 1e-3) / 16)[2] != 16 ** 3 or _run(lib, pos, (1 + 1e-3) / 16)[2] != 1:
+        if _run(lib, pos, (1 - 1e-3) / 16, parallel=parallel)[2] != 16 ** 3 or \
+                _run(lib, pos, (1 + 1e-3) / 16, parallel=parallel)[2] != 1:
             return False
         n = 20000
         pos = synth.clustered(n, 11, 0, 0.6)
         lx = synth.linking_length(0.5, n)
-        if not np.array_equal(_run(lib, pos, lx)[0], scipy_labels(pos, lx)):
+        l, s, g = _run(lib, pos, lx, parallel=parallel)
+        if not np.array_equal(l, scipy_labels(pos, lx)):
             return False
+        check_invariants(l, s, g)
         pos = synth.uniform(2048, 5)
         for b in (0.9, 1.5):
             lx = synth.linking_length(b, 2048)
-            if not np.array_equal(_run(lib, pos, lx)[0], _run(lib, pos, lx, brute=True)[0]):
+            if not np.array_equal(_run(lib, pos, lx, parallel=parallel)[0], _run(lib, pos, lx, brute=True)[0]):
                 return False
         return True
     except AssertionError:
@@ -357,9 +428,18 @@ def _pins_pass(lib) -> bool:
 
 def test_pins_pass_on_the_real_oracle():
     assert _pins_pass(oracle._load())
+    assert _pins_pass(oracle._load(), parallel=True)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistake_is_caught(name):
     with tempfile.TemporaryDirectory() as tmp:
         assert not _pins_pass(_mutant_lib(name, tmp)), f"mutant {name} passed every pin"
+
+
+@pytest.mark.parametrize("name", sorted(PARALLEL_MUTANTS))
+def test_planted_mistake_in_the_threaded_oracle_is_caught(name):
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _mutant_lib(name, tmp, PARALLEL_MUTANTS)
+        assert _pins_pass(lib), "the sequential functions are untouched"
+        assert not _pins_pass(lib, parallel=True), f"mutant {name} passed every pin"
