@@ -440,10 +440,10 @@ int oracle_fof_parallel(int64_t n, const float *pos, double L, double lx, int st
     uint32_t *first = (uint32_t *)calloc((size_t)ncell + 1, sizeof(uint32_t));
     float *spos = (float *)malloc(sizeof(float) * 3 * (size_t)n);
     int32_t *orig = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    int32_t *parent = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *parent = NULL;
     link_list *lists = (link_list *)calloc((size_t)nc, sizeof(link_list));
-    if (!cell || !first || !spos || !orig || !parent || !lists) {
-        free(cell); free(first); free(spos); free(orig); free(parent); free(lists);
+    if (!cell || !first || !spos || !orig || !lists) {
+        free(cell); free(first); free(spos); free(orig); free(lists);
         return ORACLE_ERR_MEM;
     }
 
@@ -506,7 +506,14 @@ int oracle_fof_parallel(int64_t n, const float *pos, double L, double lx, int st
         }
     }
 
+    free(spos);
+    free(first);
+
     /* 4. union-find over slots */
+    if (status == ORACLE_OK) {
+        parent = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        if (!parent) status = ORACLE_ERR_MEM;
+    }
     if (status == ORACLE_OK) {
         for (int64_t s = 0; s < n; ++s) parent[s] = (int32_t)s;
         for (int64_t cz = 0; cz < nc; ++cz)
@@ -515,8 +522,6 @@ int oracle_fof_parallel(int64_t n, const float *pos, double L, double lx, int st
     }
     for (int64_t cz = 0; cz < nc; ++cz) free(lists[cz].pair);
     free(lists);
-    free(spos);
-    free(first);
 
     /* 5. outputs: root of every slot (paths fully compressed by the first
      * pass), smallest input index and member count per root */

@@ -490,6 +490,7 @@ def test_single_box_graph_survives_other_runs():
     try:
         p0 = p[:n0].contiguous()
         label, size = f.outputs(n0)
+        f.run(p, w.offsets, w.box, w.lx)          # sizes the workspace for the larger run
         f.capture(p0, [0, n0], w.box[0], w.lx[0], label, size)
         f.run(p, w.offsets, w.box, w.lx)          # a multi-box run on the same workspace
         label.fill_(-7)
