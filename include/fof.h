@@ -244,6 +244,39 @@ fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_
                              int32_t *d_group_index, int32_t *d_group_size);
 fof_status fof_graph_launch(fof_ctx *ctx);
 
+/* Device scratch of fof_label_noalloc on each GPU (bytes). */
+#define FOF_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): fof_build_cells +
+ * fof_link + fof_finalize of ONE box (n particles, side `box`, linking length
+ * `lx`) in one call, on a scratch array the library holds in device memory,
+ * FOF_NOALLOC_SCRATCH_BYTES on each GPU it runs on (taken when the library's
+ * code is loaded onto that GPU and held until the process ends), instead of a
+ * caller's workspace. No context is needed and nothing is allocated: no
+ * device or host memory, no events. Same kernels, same results (labels,
+ * sizes, group count) as the three calls with a workspace.
+ * opt: options (NULL = defaults); collect_timings must be 0; collect_stats
+ * counts on the device but the counters are not readable. hip_stream: the
+ * stream to enqueue on (NULL = the null stream), on the current device.
+ * d_pos [n][3] FP32, d_group_index and d_group_size [n] int32: device
+ * memory owned by the caller, as for the workspace path. If h_n_groups is not
+ * NULL it receives the group count and the call waits for the stream (a
+ * latched coordinate error is returned then); otherwise it returns after
+ * enqueueing. Every call on one GPU uses that GPU's single scratch array:
+ * calls that overlap in time on one GPU (other host threads, or other
+ * streams before the previous call's work has finished) race and give
+ * undefined results; calls ordered on one stream are safe, and each call
+ * clears what it needs, whatever the previous call left.
+ * Errors, all before any device work: FOF_ERR_INVALID_ARG (bad options,
+ * collect_timings set, n < 0 or > 2^31 - 1, a null pointer with n > 0, bad
+ * box or linking length), FOF_ERR_UNSUPPORTED (the run needs more than
+ * FOF_NOALLOC_SCRATCH_BYTES -- fof_workspace_bytes gives the need for the
+ * same options and box -- or too many cells); FOF_ERR_DEVICE (no device, or
+ * the scratch address could not be found). */
+fof_status fof_label_noalloc(const fof_options *opt, void *hip_stream, const float *d_pos, int64_t n, double box,
+                             double lx, int32_t *d_group_index, int32_t *d_group_size, int64_t *h_n_groups);
+
 /* Waits for the stream and returns, per kernel of the pipeline, the summed
  * device time (ms, from HIP events recorded around each launch on the
  * context's stream) and the number of launches since the previous call; the

@@ -66,7 +66,8 @@ _lib = None
 EXPORTS = ["fof_default_options", "fof_create", "fof_set_stream", "fof_workspace_bytes", "fof_set_workspace",
            "fof_build_cells", "fof_link", "fof_finalize", "fof_read_n_groups", "fof_get_stats",
            "fof_graph_capture", "fof_graph_launch", "fof_destroy", "fof_status_string", "fof_get_kernel_times",
-           "fof_kernel_name", "fof_describe_box", "fof_catalogue", "fof_relink"]
+           "fof_kernel_name", "fof_describe_box", "fof_catalogue", "fof_relink", "fof_label_noalloc"]
+NOALLOC_SCRATCH_BYTES = 128 << 20   # FOF_NOALLOC_SCRATCH_BYTES
 
 
 def load_library():
@@ -100,6 +101,8 @@ def load_library():
                                             ctypes.POINTER(BoxInfo)]),
         "fof_catalogue": (ctypes.c_int, [vp, vp, vp, i32, vp, vp, vp, i64, i64p]),
         "fof_relink": (ctypes.c_int, [vp, f64p, i32]),
+        "fof_label_noalloc": (ctypes.c_int, [ctypes.POINTER(Options), vp, vp, i64, ctypes.c_double, ctypes.c_double,
+                                             vp, vp, i64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -252,6 +255,20 @@ def fof_relink(ctx, lx, n_boxes: int):
     l = _arr(np.broadcast_to(np.asarray(lx, dtype=np.float64), (int(n_boxes),)), np.float64)
     _check(load_library().fof_relink(ctx, l.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_boxes)),
            "fof_relink")
+
+
+def fof_label_noalloc(pos, box, lx, group_index, group_size, opt: Options | None = None, stream: int | None = None,
+                      sync: bool = True):
+    """One box through the library's own device scratch (no workspace, no
+    allocation; see include/fof.h). Returns the group count when sync."""
+    ng = ctypes.c_int64(0)
+    n = 0 if pos is None else int(pos.shape[0])
+    _check(load_library().fof_label_noalloc(ctypes.byref(opt) if opt is not None else None,
+                                            ctypes.c_void_p(stream or 0), ctypes.c_void_p(_dptr(pos)), n,
+                                            float(box), float(lx), ctypes.c_void_p(_dptr(group_index)),
+                                            ctypes.c_void_p(_dptr(group_size)),
+                                            ctypes.byref(ng) if sync else None), "fof_label_noalloc")
+    return int(ng.value) if sync else None
 
 
 def fof_kernel_name(k: int) -> str:

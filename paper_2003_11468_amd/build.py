@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfof_gfx950.so")
-SOURCES = ["fof_kernels.hip", "fof_link.hip", "fof_api.cpp"]
+SOURCES = ["fof_kernels.hip", "fof_link.hip", "fof_api.cpp", "fof_noalloc.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -547,6 +547,30 @@ fof_status read_back(fof_ctx *c, int64_t *h_n_groups, Counters *h_counters)
 
 }  // namespace
 
+namespace fof {
+
+fof_status plan_one_box(const fof_options &o, int64_t n, double box, double lx, void *ws, size_t bytes, Plan *out,
+                        size_t *need)
+{
+    *need = 0;
+    if (!options_valid(o)) return FOF_ERR_INVALID_ARG;
+    if (n < 0 || n > (int64_t)INT32_MAX) return FOF_ERR_INVALID_ARG;
+    BoxDev b;
+    fof_status st = box_geometry(o, n, box, lx, 0, &b);
+    if (st != FOF_OK) return st;
+    b.p0 = 0;
+    b.p1 = n;
+    Layout lay;
+    st = make_layout(o, n, (int64_t)b.nc * b.nc * b.nc, 1, &lay);
+    if (st != FOF_OK) return st;
+    *need = lay.total;
+    if (lay.total > bytes) return FOF_OK;
+    carve(o, lay, b, ws, out);
+    return FOF_OK;
+}
+
+}  // namespace fof
+
 extern "C" {
 
 void fof_default_options(fof_options *opt)

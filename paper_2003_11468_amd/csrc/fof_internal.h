@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/fof.h"
+
 namespace fof {
 
 // The edge list is split into slices with a counter each, so that no single
@@ -147,5 +149,12 @@ hipError_t launch_finalize(const Plan &p, hipStream_t stream, KernelTimer *t);
 // p.bucket_hist[p.n_tiles].
 hipError_t launch_catalogue(const Plan &p, const int32_t *label, const int32_t *size, int min_size,
                             int32_t *g_first, int32_t *g_size, int32_t *g_box, int64_t capacity, hipStream_t stream);
+
+// One box of n particles on a workspace chosen by the caller (fof_api.cpp):
+// validates the options and the box like fof_workspace_bytes, returns in
+// *need the bytes the run needs and, when they fit in `bytes`, fills *out
+// with the launch parameters (positions and outputs left unset).
+fof_status plan_one_box(const fof_options &o, int64_t n, double box, double lx, void *ws, size_t bytes, Plan *out,
+                        size_t *need);
 
 }  // namespace fof

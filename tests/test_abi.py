@@ -205,3 +205,25 @@ def test_tune_workload_key_and_cache(tmp_path):
     tune._save(path, {"a": {"cell_factor": 2.0, "dense_min": 16}})
     assert tune._load(path)["a"]["dense_min"] == 16
     assert tune._load(str(tmp_path / "missing.json")) == {}
+
+
+def test_noalloc_host_validation():
+    """fof_label_noalloc rejects bad arguments and oversize runs on the host,
+    before it looks for a device (none here)."""
+    lib = fof.load_library()
+    ng = ctypes.c_int64(0)
+    st = lib.fof_label_noalloc(None, None, None, 10, 1.0, 0.1, None, None, ctypes.byref(ng))
+    assert st == fof.FOF_ERR_INVALID_ARG                  # positions and outputs missing
+    fake = ctypes.c_void_p(0x10000)
+    for n, box, lx in ((-1, 1.0, 0.1), (10, 1.0, 0.0), (10, 0.0, 0.1), (10, 1.0, 0.4)):
+        assert lib.fof_label_noalloc(None, None, fake, n, box, lx, fake, fake, None) == fof.FOF_ERR_INVALID_ARG
+    n = 4_000_000
+    assert lib.fof_label_noalloc(None, None, fake, n, 1.0, 0.2 / n ** (1 / 3), fake, fake, None) \
+        == fof.FOF_ERR_UNSUPPORTED
+    o = fof.make_options(timings=True)
+    assert lib.fof_label_noalloc(ctypes.byref(o), None, fake, 10, 1.0, 0.1, fake, fake, None) \
+        == fof.FOF_ERR_INVALID_ARG
+    o = fof.fof_default_options()
+    o.predicate = 9
+    assert lib.fof_label_noalloc(ctypes.byref(o), None, fake, 10, 1.0, 0.1, fake, fake, None) \
+        == fof.FOF_ERR_INVALID_ARG
