@@ -100,6 +100,13 @@ typedef struct {
                                 1 = randomised linking: by a fixed pseudo-random priority of the index
                                 (a bijection), a contention variant. Same labels either way: the label
                                 is the smallest original index of the group, whatever its root */
+    int32_t schedule;        /* work schedule of the link pass, bit fields (0 = defaults; changes speed only):
+                                bits 0-1: work-groups of the per-particle search (1024, 512, 2048, 4096);
+                                bits 2-3: work-groups of the wavefront search (2048, 1024, 4096, 8192);
+                                bit 4: no sub-cell pre-merge of dense cells (see fof_box_info) */
+    int32_t compression;     /* path compression of the finds (paper, Section 3.4.3): 0 = path halving
+                                (each visited node re-pointed to its grandparent; default); 1 = a path is
+                                compressed onto its root only when it is at least 2 long. Same labels */
     int32_t reserved[2];     /* must be zero */
 } fof_options;
 

@@ -40,7 +40,8 @@ class Options(ctypes.Structure):
     _fields_ = [("predicate", ctypes.c_int32), ("strict_less", ctypes.c_int32), ("cell_factor", ctypes.c_double),
                 ("collect_stats", ctypes.c_int32), ("dense_min", ctypes.c_int32), ("collect_timings", ctypes.c_int32),
                 ("sort_segment_log2", ctypes.c_int32), ("domains", ctypes.c_int32),
-                ("link_order", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("link_order", ctypes.c_int32), ("schedule", ctypes.c_int32), ("compression", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -281,10 +282,23 @@ def fof_status_string(status: int) -> str:
 
 # ------------------------------------------------------ tensor wrapper --
 
+COMPRESSIONS = {"halving": 0, "depth2": 1}   # fof_options.compression
+
+
+def schedule_bits(sparse_grid: int = 1024, dense_grid: int = 2048, premerge: bool = True) -> int:
+    """fof_options.schedule from its parts (grids of the two persistent link kernels, pre-merge)."""
+    sg = {1024: 0, 512: 1, 2048: 2, 4096: 3}[int(sparse_grid)]
+    dg = {2048: 0, 1024: 1, 4096: 2, 8192: 3}[int(dense_grid)]
+    return sg | (dg << 2) | (0 if premerge else 16)
+
+
 def make_options(predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
                  stats: bool = False, dense_min: int = 0, timings: bool = False, segment_log2: int = 0,
-                 domains: int = 0, link_order: str = "index") -> Options:
+                 domains: int = 0, link_order: str = "index", schedule: int = 0,
+                 compression: str = "halving") -> Options:
     o = fof_default_options()
+    o.schedule = int(schedule)
+    o.compression = COMPRESSIONS[compression]
     o.sort_segment_log2 = int(segment_log2)
     o.domains = int(domains)
     o.link_order = LINK_ORDERS[link_order]
@@ -302,13 +316,14 @@ class FoF:
 
     def __init__(self, predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,
                  stats: bool = False, stream=None, dense_min: int = 0, timings: bool = False,
-                 segment_log2: int = 0, domains: int = 0, link_order: str = "index"):
+                 segment_log2: int = 0, domains: int = 0, link_order: str = "index", schedule: int = 0,
+                 compression: str = "halving"):
         import torch
 
         self._torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.ctx = fof_create(make_options(predicate, strict, cell_factor, stats, dense_min, timings, segment_log2,
-                                           domains, link_order), self.stream.cuda_stream)
+                                           domains, link_order, schedule, compression), self.stream.cuda_stream)
         self.ws = None
         self._graph_refs = None   # tensors a captured graph reads or writes
 

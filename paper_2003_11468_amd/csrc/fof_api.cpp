@@ -167,6 +167,8 @@ bool options_valid(const fof_options &o)
         return false;
     if (o.domains < 0 || o.domains > kMaxDomains) return false;
     if (o.link_order != 0 && o.link_order != 1) return false;
+    if (o.schedule < 0 || o.schedule >= 32) return false;
+    if (o.compression != 0 && o.compression != 1) return false;
     for (int k = 0; k < 2; ++k)
         if (o.reserved[k] != 0) return false;
     return true;
@@ -393,8 +395,12 @@ void carve(const fof_options &o, const Layout &p, const BoxDev &box0, void *ws, 
     d.sub_log2 = p.sub_log2;
     d.n_segments = p.n_segments;
     d.dense_min = dense_min_of(o);
-    d.dense_blocks = kDenseBlocks;
-    d.sparse_blocks = kSparseBlocks;
+    static const int32_t sparse_grid[4] = {kSparseBlocks, kSparseBlocks / 2, kSparseBlocks * 2, kSparseBlocks * 4};
+    static const int32_t dense_grid[4] = {kDenseBlocks, kDenseBlocks / 2, kDenseBlocks * 2, kDenseBlocks * 4};
+    d.sparse_blocks = sparse_grid[o.schedule & 3];
+    d.dense_blocks = dense_grid[(o.schedule >> 2) & 3];
+    d.premerge = (o.schedule & 16) ? 0 : 1;
+    d.find_mode = o.compression;
     d.domains = o.domains > 1 ? o.domains : 0;
     d.link_random = o.link_order == 1 ? 1 : 0;
     d.max_items = p.max_items;

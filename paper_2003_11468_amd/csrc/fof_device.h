@@ -72,18 +72,32 @@ __device__ __forceinline__ bool link_fp64(float ax, float ay, float az, float bx
 }
 
 // ------------------------------------------------------------ union-find --
-// parent[] is read and written with device-scope relaxed atomics: the eight
-// XCDs have private L2 caches, and plain loads could keep returning a stale
-// line while other XCDs hook roots.
+// The forest's reads and path-halving writes go through the XCD's own L2
+// (relaxed atomics of work-group scope: they skip the compute unit's L1 but
+// not the L2); only the hooking compare-and-swap is device-wide. A read may
+// then return an older value, which is still safe:
+//  - parent pointers only move to nodes of smaller hooking key (a hook puts a
+//    root under a root of smaller key; halving puts a node under an
+//    ancestor), so every chain of values read, current or older, has
+//    strictly decreasing keys: a find ends, and never runs in a cycle;
+//  - sets only merge, so every node reached from x is in x's set: a find
+//    returns a node of x's set, and two finds that meet prove one set;
+//  - a node seen as a non-root stays one, so halving never writes a root, and
+//    the compare-and-swap (device scope, expecting the root itself) alone
+//    decides whether a root is still a root. A stale root makes it fail and
+//    return the current parent, whose key is smaller: each failure lowers the
+//    largest key the next attempt can target, so merging ends too.
+// Reading through the L2 keeps the neighbouring nodes of a find (nearby in
+// cell order) in cache, instead of a trip past the L2 per step.
 
 __device__ __forceinline__ int ld_rel(const int *a)
 {
-    return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ void st_rel(int *a, int v)
 {
-    __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Root of x with path halving: each visited node is re-pointed to its
@@ -118,15 +132,45 @@ __device__ __forceinline__ unsigned link_key(int x, bool random)
     return h;
 }
 
+// Root of x, compressing the path only when it is at least 2 long (paper,
+// Section 3.4.3): a first walk to the root, then, for a long path, a second
+// walk that points its nodes at the root. A node is re-pointed only while it
+// is not a root and only to a node of smaller key (the root found lies in its
+// set), so the forest stays valid whatever other finds and hooks do.
+__device__ __forceinline__ int find_depth2(int *parent, int x, bool random)
+{
+    int r = x, depth = 0;
+    for (int q = ld_rel(parent + r); q != r; q = ld_rel(parent + r)) {
+        r = q;
+        ++depth;
+    }
+    if (depth >= 2) {
+        const unsigned kr = link_key(r, random);
+        for (int y = x;;) {
+            const int ny = ld_rel(parent + y);
+            if (ny == y || ny == r) break;
+            if (kr < link_key(y, random)) st_rel(parent + y, r);
+            y = ny;
+        }
+    }
+    return r;
+}
+
+// The find of the run's compression mode (0: halving, 1: depth >= 2).
+__device__ __forceinline__ int find_root(int *parent, int x, int mode, bool random)
+{
+    return mode == 1 ? find_depth2(parent, x, random) : find_halve(parent, x);
+}
+
 // Merge the groups of a and b: hook the root of lower priority under the other
 // with a compare-and-swap that expects it to still be a root. On failure the
 // CAS returns the node's new parent, and the search continues from there.
-__device__ __forceinline__ unsigned unite(int *parent, int a, int b, bool random)
+__device__ __forceinline__ unsigned unite(int *parent, int a, int b, bool random, int mode = 0)
 {
     unsigned retries = 0;
     while (true) {
-        a = find_halve(parent, a);
-        b = find_halve(parent, b);
+        a = find_root(parent, a, mode, random);
+        b = find_root(parent, b, mode, random);
         if (a == b) return retries;
         const bool a_first = link_key(a, random) < link_key(b, random);
         int lo = a_first ? a : b;

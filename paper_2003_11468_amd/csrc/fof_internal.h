@@ -64,6 +64,8 @@ struct Plan {
     int32_t sparse_blocks;  // grid of the persistent sparse link kernel
     int32_t domains;        // > 1: slabs along x, local union-find per slab, then a global merge
     int32_t link_random;    // 1: roots hook by a pseudo-random priority of the index, not the index
+    int32_t premerge;       // 1: dense cells are pre-merged by sub-cells before the wavefront search
+    int32_t find_mode;      // 0: finds halve paths; 1: a path of length >= 2 is compressed onto its root
     int64_t max_items;      // capacity of `items`
     int64_t max_edges;      // capacity of `edges`: kEdgeSlices slices of max_edges / kEdgeSlices
 

@@ -45,11 +45,11 @@ __device__ __forceinline__ float qnan() { return __builtin_nanf(""); }
 
 // Merge the groups that contain roots-or-members a and b; returns a node of the
 // merged group (the root that stayed a root at the time of the merge).
-__device__ __forceinline__ int unite_root(int *parent, int a, int b, bool random, unsigned &retries)
+__device__ __forceinline__ int unite_root(int *parent, int a, int b, bool random, int mode, unsigned &retries)
 {
     while (true) {
-        a = find_halve(parent, a);
-        b = find_halve(parent, b);
+        a = find_root(parent, a, mode, random);
+        b = find_root(parent, b, mode, random);
         if (a == b) return a;
         const bool a_first = link_key(a, random) < link_key(b, random);
         const int lo = a_first ? a : b;
@@ -92,7 +92,7 @@ __device__ __forceinline__ void defer_boundary(const Plan &p, int a, int b, unsi
 {
     const unsigned at = atomicAdd(&p.counters->n_boundary, 1u);
     if ((int64_t)at < p.max_edges) p.bnd[at] = make_int2(a, b);
-    else retries += unite(p.parent, a, b, p.link_random);
+    else retries += unite(p.parent, a, b, p.link_random, p.find_mode);
 }
 
 // Merge of a linked pair found by the search: at once, or in domain mode
@@ -100,7 +100,7 @@ __device__ __forceinline__ void defer_boundary(const Plan &p, int a, int b, unsi
 __device__ __forceinline__ void merge_pair(const Plan &p, int a, int b, unsigned &retries)
 {
     if (p.domains > 1 && domain_of(p, a) != domain_of(p, b)) defer_boundary(p, a, b, retries);
-    else retries += unite(p.parent, a, b, p.link_random);
+    else retries += unite(p.parent, a, b, p.link_random, p.find_mode);
 }
 
 // --------------------------------------------------------- sparse (lane) --
@@ -520,17 +520,26 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
     }
 }
 
-// Merges the queued pairs: one thread per pair, no ordering needed.
+// Merges the queued pairs: one thread per pair, no ordering needed. Slice s
+// holds the pairs found on XCD s % 8 (the search's work-group b appends to
+// slice b % 256, and work-groups go to XCDs round-robin), whose home
+// particles are that XCD's contiguous range of cells; its kUnionParts
+// work-groups run on the same XCD, so the finds of a slice stay in one L2.
+constexpr int kUnionParts = 16;
+static_assert(kEdgeSlices % kXcds == 0, "slices split evenly over the XCDs");
+
 template <bool kStats>
 __global__ void __launch_bounds__(kBlock) k_union_edges(Plan p)
 {
-    const int slice = blockIdx.y;
+    const int xcd = blockIdx.x % kXcds, g = blockIdx.x / kXcds;
+    const int slice = (g % (kEdgeSlices / kXcds)) * kXcds + xcd;
+    const int part = g / (kEdgeSlices / kXcds);
     const int64_t cap = p.max_edges / kEdgeSlices;
     const unsigned fill = p.edge_fill[slice];
     const int64_t ne = (int64_t)fill < cap ? (int64_t)fill : cap;
     const int2 *edges = p.edges + slice * cap;
     unsigned retries = 0;
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < ne; k += (int64_t)gridDim.x * kBlock) {
+    for (int64_t k = (int64_t)part * kBlock + threadIdx.x; k < ne; k += (int64_t)kUnionParts * kBlock) {
         const int2 e = edges[k];
         merge_pair(p, e.x, e.y, retries);
     }
@@ -538,7 +547,7 @@ __global__ void __launch_bounds__(kBlock) k_union_edges(Plan p)
         unsigned long long r = wave_sum_u64((unsigned long long)retries);
         if (lane_id() == 0 && r) atomicAdd(&p.counters->cas_retries, r);
         // queued pairs, for the statistics
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&p.counters->n_edges, fill);
+        if (part == 0 && threadIdx.x == 0) atomicAdd(&p.counters->n_edges, fill);
     }
 }
 
@@ -573,14 +582,22 @@ struct BoxRegs {
 
 // The slow path of one staged candidate kk for the lanes in `cand`: an FP32
 // result below lo32 links; one inside the band is re-decided in double from
-// the original coordinates; a link merges the groups unless the cached roots
-// already agree. kGeneral: domain mode (a link across slabs goes to the
+// the original coordinates; a link merges the groups unless they are already
+// known to be one. kGeneral: domain mode (a link across slabs goes to the
 // boundary list) and randomised linking, decided at run time; the plain
 // instance has neither, which keeps its registers and code size down.
+//
+// Known roots: root_i is the root last seen for the home particle; known0
+// and known1 are two more nodes of its group (the two roots of its last
+// merge). A candidate whose cached root is any of them is in the group
+// already (groups only grow), so the pair needs no union whatever its
+// distance. Without statistics the caller drops such candidates before the
+// distance decides anything.
 template <bool kFP64, bool kStats, bool kGeneral>
 __device__ __forceinline__ void dense_hit(const Plan &p, const BoxRegs &br, const typename Stage<kFP64>::T &st,
-                                          int kk, int jb, bool cand, float r, float4 pi, int &root_i,
-                                          unsigned long long &links, unsigned long long &band, unsigned &retries)
+                                          int kk, int jb, bool cand, float r, float4 pi, int &root_i, int &known0,
+                                          int &known1, unsigned long long &links, unsigned long long &band,
+                                          unsigned &retries)
 {
     if (!cand) return;
     const int j = jb + kk;
@@ -597,18 +614,22 @@ __device__ __forceinline__ void dense_hit(const Plan &p, const BoxRegs &br, cons
         int rj;
         if constexpr (kFP64) rj = st.root[kk];
         else rj = __float_as_int(st.v[kk].w);
-        if (rj != root_i) {
-            if (kGeneral && p.domains > 1 && domain_of(p, j) != slab_of(pi.x, p.domains, br.L))
+        if (rj != root_i && rj != known0 && rj != known1) {
+            if (kGeneral && p.domains > 1 && domain_of(p, j) != slab_of(pi.x, p.domains, br.L)) {
                 defer_boundary(p, root_i, rj, retries);
-            else root_i = unite_root(p.parent, root_i, rj, kGeneral && p.link_random, retries);
+            } else {
+                const int old = root_i;
+                root_i = unite_root(p.parent, root_i, rj, kGeneral && p.link_random, p.find_mode, retries);
+                known0 = rj;
+                known1 = old;
+            }
         }
     }
 }
 
-// FP32 squared distance of the home lane to staged candidate kk.
-__device__ __forceinline__ float dist2_f32(const StageF &st, int kk, float hx, float hy, float hz)
+// FP32 squared distance of the home lane to a staged candidate.
+__device__ __forceinline__ float dist2_f32(const float4 cj, float hx, float hy, float hz)
 {
-    const float4 cj = st.v[kk];
     const float dx = hx - cj.x, dy = hy - cj.y, dz = hz - cj.z;
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
@@ -627,23 +648,31 @@ __device__ __forceinline__ bool link_f64_staged(const StageD &st, int kk, double
 }
 
 // Tests the staged candidates [0, cnt) against the wave's home particles.
-// kSelf: the candidates come from the home cell; only j > i counts.
+// kSelf: the candidates come from the home cell; only j > i counts. Without
+// statistics a candidate whose cached root is known to be in the home
+// particle's group is dropped together with the distance test's verdict, so
+// once a halo's groups have merged the batch runs without branching.
 template <bool kFP64, bool kStats, bool kGeneral, bool kSelf>
 __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, const typename Stage<kFP64>::T &st,
                                             int cnt, int jb, int i, bool vi, float4 pi, float hx, float hy,
                                             float hz, double dxi, double dyi, double dzi, double Lx, double Ly,
-                                            double Lz, int &root_i, unsigned long long &links,
-                                            unsigned long long &band, unsigned &retries)
+                                            double Lz, int &root_i, int &known0, int &known1,
+                                            unsigned long long &links, unsigned long long &band, unsigned &retries)
 {
     const int rel = i - jb;   // candidate kk is above the home particle iff kk > rel
+    auto fresh = [&](int rj) { return kStats || (rj != root_i && rj != known0); };
     int kk = 0;
     if constexpr (!kFP64) {
         for (; kk + 4 <= cnt; kk += 4) {
-            const float r0 = dist2_f32(st, kk + 0, hx, hy, hz);
-            const float r1 = dist2_f32(st, kk + 1, hx, hy, hz);
-            const float r2 = dist2_f32(st, kk + 2, hx, hy, hz);
-            const float r3 = dist2_f32(st, kk + 3, hx, hy, hz);
-            bool c0 = r0 <= br.hi32, c1 = r1 <= br.hi32, c2 = r2 <= br.hi32, c3 = r3 <= br.hi32;
+            const float4 q0 = st.v[kk + 0], q1 = st.v[kk + 1], q2 = st.v[kk + 2], q3 = st.v[kk + 3];
+            const float r0 = dist2_f32(q0, hx, hy, hz);
+            const float r1 = dist2_f32(q1, hx, hy, hz);
+            const float r2 = dist2_f32(q2, hx, hy, hz);
+            const float r3 = dist2_f32(q3, hx, hy, hz);
+            bool c0 = r0 <= br.hi32 && fresh(__float_as_int(q0.w));
+            bool c1 = r1 <= br.hi32 && fresh(__float_as_int(q1.w));
+            bool c2 = r2 <= br.hi32 && fresh(__float_as_int(q2.w));
+            bool c3 = r3 <= br.hi32 && fresh(__float_as_int(q3.w));
             if constexpr (kSelf) {
                 c0 = c0 && kk + 0 > rel;
                 c1 = c1 && kk + 1 > rel;
@@ -651,10 +680,14 @@ __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, co
                 c3 = c3 && kk + 3 > rel;
             }
             if (__ballot(c0 || c1 || c2 || c3)) {
-                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 0, jb, c0, r0, pi, root_i, links, band, retries);
-                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 1, jb, c1, r1, pi, root_i, links, band, retries);
-                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 2, jb, c2, r2, pi, root_i, links, band, retries);
-                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 3, jb, c3, r3, pi, root_i, links, band, retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 0, jb, c0, r0, pi, root_i, known0, known1, links,
+                                                   band, retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 1, jb, c1, r1, pi, root_i, known0, known1, links,
+                                                   band, retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 2, jb, c2, r2, pi, root_i, known0, known1, links,
+                                                   band, retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 3, jb, c3, r3, pi, root_i, known0, known1, links,
+                                                   band, retries);
             }
         }
     }
@@ -662,13 +695,16 @@ __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, co
         bool c;
         float r = 0.f;
         if constexpr (kFP64) {
-            c = vi && link_f64_staged(st, kk, dxi, dyi, dzi, Lx, Ly, Lz, br);
+            c = vi && fresh(st.root[kk]) && link_f64_staged(st, kk, dxi, dyi, dzi, Lx, Ly, Lz, br);
         } else {
-            r = dist2_f32(st, kk, hx, hy, hz);
-            c = r <= br.hi32;   // false for invalid (NaN) lanes and candidates
+            const float4 q = st.v[kk];
+            r = dist2_f32(q, hx, hy, hz);
+            c = r <= br.hi32 && fresh(__float_as_int(q.w));   // false for invalid (NaN) lanes and candidates
         }
         if constexpr (kSelf) c = c && kk > rel;
-        if (__ballot(c)) dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk, jb, c, r, pi, root_i, links, band, retries);
+        if (__ballot(c))
+            dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk, jb, c, r, pi, root_i, known0, known1, links, band,
+                                               retries);
     }
 }
 
@@ -700,11 +736,26 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
         const float L32 = bd.L32;
         const int local = c - cb;
         const int cx = local % nc, cy = (local / nc) % nc, cz = local / (nc * nc);
-        const int ce = __builtin_amdgcn_readfirstlane(cell_span(p, c).y);
+        // the slots of the 27 neighbour cells, one cell per lane (lanes 0-26,
+        // neighbour nb = 9 (dz + 1) + 3 (dy + 1) + dx + 1), all looked up at once
+        int nb_j0 = 0, nb_j1 = 0;
+        if (lane < 27) {
+            int nx = cx + lane % 3 - 1, ny = cy + (lane / 3) % 3 - 1, nz = cz + lane / 9 - 1;
+            nx += nx < 0 ? nc : (nx >= nc ? -nc : 0);
+            ny += ny < 0 ? nc : (ny >= nc ? -nc : 0);
+            nz += nz < 0 ? nc : (nz >= nc ? -nc : 0);
+            const int2 sp = cell_span(p, cb + (nz * nc + ny) * nc + nx);
+            nb_j0 = sp.x;
+            nb_j1 = sp.y;
+        }
+        const int ce = __shfl(nb_j1, 13, 64);   // the cell itself
         const int i = first + lane;
         const bool vi = i < ce;
         const float4 pi = vi ? p.sorted[i] : make_float4(qnan(), qnan(), qnan(), 0.f);
-        int root_i = vi ? find_halve(p.parent, i) : -1;
+        const bool rnd = kGeneral && p.link_random;
+        const int mode = p.find_mode;
+        int root_i = vi ? find_root(p.parent, i, mode, rnd) : -1;
+        int known0 = -3, known1 = -3;   // never a node
         const double dxi = (double)pi.x, dyi = (double)pi.y, dzi = (double)pi.z;
         const int n_home = min(64, ce - first);
 
@@ -722,10 +773,8 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
             else if (ny >= nc) { ny -= nc; hy = pi.y - L32; Ly = -br.L; }
             if (nz < 0) { nz += nc; sz = L32; Lz = br.L; }
             else if (nz >= nc) { nz -= nc; hz = pi.z - L32; Lz = -br.L; }
-            const int c2 = cb + (nz * nc + ny) * nc + nx;
-            const int2 sp = cell_span(p, c2);
-            int j0 = __builtin_amdgcn_readfirstlane(sp.x);
-            const int j1 = __builtin_amdgcn_readfirstlane(sp.y);
+            int j0 = __builtin_amdgcn_readfirstlane(__shfl(nb_j0, nb, 64));
+            const int j1 = __builtin_amdgcn_readfirstlane(__shfl(nb_j1, nb, 64));
             if (self) j0 = first;
             else if (!upper && j1 - j0 >= p.dense_min) continue;   // that dense cell searches this pair
 #pragma unroll 1
@@ -733,7 +782,19 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
                 const int j = jb + lane;
                 const bool vj = j < j1;
                 const float4 q = vj ? p.sorted[j] : make_float4(qnan(), qnan(), qnan(), 0.f);
-                const int rj = vj ? find_halve(p.parent, j) : -2;
+                // the home particle's cached root, checked once per neighbour
+                // cell (other waves may have merged its group meanwhile)
+                const int pr = (!kStats && jb == j0 && vi) ? ld_rel(p.parent + root_i) : root_i;
+                const int rj = vj ? find_root(p.parent, j, mode, rnd) : -2;
+                if constexpr (!kStats) {
+                    if (pr != root_i) root_i = find_root(p.parent, pr, mode, rnd);
+                    // a batch whose candidates all have one root that every
+                    // home particle knows as its own group needs no test
+                    const int r0 = __builtin_amdgcn_readfirstlane(rj);   // lane 0 holds a candidate
+                    if (__ballot(vj && rj != r0) == 0 &&
+                        __ballot(vi && root_i != r0 && known0 != r0 && known1 != r0) == 0)
+                        continue;
+                }
                 if constexpr (kFP64) {
                     st.x[lane] = (double)q.x;
                     st.y[lane] = (double)q.y;
@@ -746,11 +807,13 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
                 const int cnt = min(64, j1 - jb);
                 if (kStats) tests += (unsigned long long)cnt * (unsigned long long)n_home;
                 if (self)
-                    dense_batch<kFP64, kStats, kGeneral, true>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi, dzi, Lx,
-                                                     Ly, Lz, root_i, links, band, retries);
+                    dense_batch<kFP64, kStats, kGeneral, true>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi,
+                                                               dzi, Lx, Ly, Lz, root_i, known0, known1, links, band,
+                                                               retries);
                 else
-                    dense_batch<kFP64, kStats, kGeneral, false>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi, dzi,
-                                                      Lx, Ly, Lz, root_i, links, band, retries);
+                    dense_batch<kFP64, kStats, kGeneral, false>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi,
+                                                                dzi, Lx, Ly, Lz, root_i, known0, known1, links, band,
+                                                                retries);
                 __builtin_amdgcn_wave_barrier();
             }
         }
@@ -815,7 +878,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
         __builtin_amdgcn_wave_barrier();
         for (int j = cs + lane; j < ce; j += 64) {
             const int r = rp[sub_of(j)];
-            if (r != j) retries += unite(p.parent, j, r, p.link_random);
+            if (r != j) retries += unite(p.parent, j, r, p.link_random, p.find_mode);
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -909,11 +972,11 @@ void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
     hipLaunchKernelGGL((k_link_sparse<kFP64, kStats>), dim3((unsigned)p.sparse_blocks), dim3(kBlock), 0, stream, p);
     if (t) t->mark(K_LINK_SPARSE, true, stream);
     if (t) t->mark(K_UNION_EDGES, false, stream);
-    hipLaunchKernelGGL((k_union_edges<kStats>), dim3(16, kEdgeSlices), dim3(kBlock), 0, stream, p);
+    hipLaunchKernelGGL((k_union_edges<kStats>), dim3(kUnionParts * kEdgeSlices), dim3(kBlock), 0, stream, p);
     if (t) t->mark(K_UNION_EDGES, true, stream);
     if (t) t->mark(K_LINK_DENSE, false, stream);
     // the sub-cell pre-merge would merge across slab faces: not in domain mode
-    if (p.domains <= 1)
+    if (p.domains <= 1 && p.premerge)
         hipLaunchKernelGGL(k_dense_premerge, dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
     if (p.domains > 1 || p.link_random)
         hipLaunchKernelGGL((k_link_dense<kFP64, kStats, true>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0,

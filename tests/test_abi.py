@@ -62,6 +62,15 @@ def test_create_rejects_bad_options():
     o = fof.fof_default_options()
     o.link_order = 1
     fof.fof_destroy(fof.fof_create(o))
+    for field, bad in (("schedule", 32), ("schedule", -1), ("compression", 2), ("compression", -1)):
+        o = fof.fof_default_options()
+        setattr(o, field, bad)
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_create(o)
+        assert e.value.status == fof.FOF_ERR_INVALID_ARG, field
+    o = fof.make_options(schedule=fof.schedule_bits(4096, 8192, False), compression="depth2")
+    assert o.schedule == 3 | (3 << 2) | 16 and o.compression == 1
+    fof.fof_destroy(fof.fof_create(o))
 
 
 def test_workspace_bytes_scales_with_particles_and_cells():

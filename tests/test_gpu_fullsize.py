@@ -33,12 +33,15 @@ def note(msg):
     print(msg, flush=True)
 
 
+OPTION_KEYS = ("cell_factor", "dense_min", "schedule", "link_order", "compression", "segment_log2")
+
+
 def tuned(pos, w, predicate="fp32_filter", **kw):
     return tune.autotune(pos, w.offsets, w.box, w.lx, predicate, cache_path=None, repeats=1, **kw)
 
 
 def run(pos, w, cfg, predicate="fp32_filter"):
-    f = fof.FoF(predicate, cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"])
+    f = fof.FoF(predicate, **{k: cfg[k] for k in OPTION_KEYS if k in cfg})
     try:
         label, size, ng = f.run(pos, w.offsets, w.box, w.lx)
         return label.cpu().numpy(), size.cpu().numpy(), ng
@@ -65,7 +68,7 @@ def test_batched256_full_size_matches_oracle_in_a_graph():
     w = synth.make("batched256")
     pos = torch.from_numpy(w.pos).cuda()
     cfg = tuned(pos, w)
-    f = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"])
+    f = fof.FoF("fp32_filter", **{k: cfg[k] for k in OPTION_KEYS if k in cfg})
     try:
         label, size = f.outputs(w.n)
         f.capture(pos, w.offsets, w.box, w.lx, label, size)
@@ -89,7 +92,7 @@ def _both_predicates_against_oracle(name, cell_factors, dense_mins):
     pos = torch.from_numpy(w.pos).cuda()
     out = {}
     for predicate in ("fp32_filter", "fp64"):
-        cfg = tuned(pos, w, predicate, cell_factors=cell_factors, dense_mins=dense_mins)
+        cfg = tuned(pos, w, predicate, cell_factors=cell_factors, dense_mins=dense_mins, axes={})
         note(f"{name}: {predicate} at cell factor {cfg['cell_factor']}, dense threshold {cfg['dense_min']}")
         out[predicate] = run(pos, w, cfg, predicate)
         torch.cuda.empty_cache()
@@ -119,7 +122,7 @@ def test_percolate1024_both_predicates_match_oracle():
 def test_lattice1024_is_one_group_under_both_link_orders():
     w = synth.make("lattice1024")
     pos = torch.from_numpy(w.pos).cuda()
-    cfg = tuned(pos, w, cell_factors=(0.0, 2.0), dense_mins=(32,))
+    cfg = tuned(pos, w, cell_factors=(0.0, 2.0), dense_mins=(32,), axes={})
     for order in ("index", "random"):
         f = fof.FoF("fp32_filter", cell_factor=cfg["cell_factor"], dense_min=cfg["dense_min"], link_order=order)
         try:

@@ -559,10 +559,48 @@ def test_autotuner_choice_is_exact(tmp_path):
     cache = str(tmp_path / "tune.json")
     r = tune.autotune(pos, [0, n], 1.0, lx, cache_path=cache, repeats=1, cell_factors=(0.0, 2.0, 3.0),
                       dense_mins=(8, 32))
-    assert not r["cached"] and len(r["tried"]) == 6
+    assert not r["cached"] and len(r["tried"]) == 6 + sum(len(v) - 1 for v in tune.AXES.values())
+    assert "gfx950" in r["key"] and "|clu" in r["key"]
     again = tune.autotune(pos, [0, n], 1.0, lx, cache_path=cache)
     assert again["cached"] and again["cell_factor"] == r["cell_factor"]
-    assert_single(pos_np, lx, cell_factor=r["cell_factor"], dense_min=r["dense_min"])
+    ref = oracle.fof(pos_np, lx)
+    f = fof.FoF(cell_factor=r["cell_factor"], dense_min=r["dense_min"], schedule=r["schedule"],
+                link_order=r["link_order"], compression=r["compression"], segment_log2=r["segment_log2"])
+    try:
+        label, size, ng = f.run(pos, [0, n], 1.0, lx)
+        assert np.array_equal(label.cpu().numpy(), ref[0]) and np.array_equal(size.cpu().numpy(), ref[1])
+    finally:
+        f.close()
+
+
+TUNER_OPTIONS = ([dict(schedule=fof.schedule_bits(sg, dg, pm)) for sg, dg, pm in
+                  ((512, 1024, True), (2048, 4096, True), (4096, 8192, True), (1024, 2048, False))] +
+                 [dict(link_order="random"), dict(compression="depth2"),
+                  dict(compression="depth2", link_order="random"), dict(segment_log2=12)])
+
+
+@pytest.mark.parametrize("opt", TUNER_OPTIONS, ids=lambda o: "-".join(f"{k}{v}" for k, v in o.items()))
+@pytest.mark.parametrize("predicate", PREDICATES)
+def test_every_tuner_option_is_exact(opt, predicate):
+    """Every work-schedule and contention option the autotuner may pick gives
+    the oracle's labels: on a batch with dense halo cells (both kernels and
+    the pre-merge run) and on a jittered lattice that is one group."""
+    w = synth.make("batched256", n_boxes=12, size_scale=0.05)
+    ref = oracle.fof_boxes(w.pos, w.offsets, w.box, w.lx)
+    f = fof.FoF(predicate, cell_factor=1.5, dense_min=16, **opt)
+    try:
+        label, size, ng = f.run(torch.from_numpy(w.pos).cuda(), w.offsets, w.box, w.lx)
+        assert np.array_equal(label.cpu().numpy(), ref[0]) and np.array_equal(size.cpu().numpy(), ref[1])
+        assert np.array_equal(ng, ref[2])
+    finally:
+        f.close()
+    lat = synth.make("lattice1024", n=64 ** 3)   # 64^3 sites, spacing 0.9 l_x: one group
+    f = fof.FoF(predicate, cell_factor=0.0, dense_min=32, **opt)
+    try:
+        label, size, ng = f.run(torch.from_numpy(lat.pos).cuda(), lat.offsets, lat.box, lat.lx)
+        assert int(ng[0]) == 1 and int(label.count_nonzero()) == 0 and int(size[0]) == lat.n
+    finally:
+        f.close()
 
 
 def test_kernel_times_cover_every_kernel():
