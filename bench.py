@@ -186,6 +186,7 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="time the headline eagerly instead of as a graph")
     ap.add_argument("--cell-factor", type=float, default=None, help="skip tuning, use this cell size")
     ap.add_argument("--dense-min", type=int, default=None, help="skip tuning, use this dense threshold")
+    ap.add_argument("--schedule", type=int, default=0, help="with --cell-factor and --dense-min: fof_options.schedule")
     ap.add_argument("--no-side", action="store_true", help="only the headline workload")
     ap.add_argument("--no-large", action="store_true", help="no 134M and 1.07B side workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -216,7 +217,8 @@ def choose(tune, pos, w, predicate, args, **kw):
     """The autotuner's configuration for this input (untimed), or the one
     given on the command line."""
     if args.cell_factor is not None and args.dense_min is not None:
-        return {"cell_factor": args.cell_factor, "dense_min": args.dense_min, "tuned": False}
+        return {"cell_factor": args.cell_factor, "dense_min": args.dense_min, "schedule": args.schedule,
+                "tuned": False}
     t0 = time.perf_counter()
     r = tune.autotune(pos, w.offsets, w.box, w.lx, predicate, cache_path=None, repeats=2, **kw)
     out = {k: r[k] for k in r if k in FOF_KEYS}

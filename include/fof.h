@@ -103,7 +103,14 @@ typedef struct {
     int32_t schedule;        /* work schedule of the link pass, bit fields (0 = defaults; changes speed only):
                                 bits 0-1: work-groups of the per-particle search (1024, 512, 2048, 4096);
                                 bits 2-3: work-groups of the wavefront search (2048, 1024, 4096, 8192);
-                                bit 4: no sub-cell pre-merge of dense cells (see fof_box_info) */
+                                bit 4: no sub-cell pre-merge of dense cells (see fof_box_info);
+                                bit 5: giant-component skip (a contention variant in the manner of
+                                Afforest, Sutton et al. 2018): the per-particle search first links each
+                                particle to its three axis-neighbour cells only, the largest group is
+                                found from a sample of 4096 roots, then the full periodic shell is
+                                searched, both ways, from the particles outside that group alone (pairs
+                                inside it are never visited). Pays off when one group spans most of the
+                                box; not with domains > 1 */
     int32_t compression;     /* path compression of the finds (paper, Section 3.4.3): 0 = path halving
                                 (each visited node re-pointed to its grandparent; default); 1 = a path is
                                 compressed onto its root only when it is at least 2 long. Same labels */

@@ -54,7 +54,7 @@ struct Layout {
     int64_t max_edges = 0;
     // workspace layout (byte offsets)
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_kmap = 0, o_sorted = 0,
-           o_perm = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
+           o_orig = 0, o_gmin = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
            o_stpos = 0, o_wave_roots = 0, o_occ = 0, o_edge_fill = 0, o_seg = 0, o_staging2 = 0,
            o_stage2_k = 0, o_bnd = 0, total = 0;
 };
@@ -167,7 +167,8 @@ bool options_valid(const fof_options &o)
         return false;
     if (o.domains < 0 || o.domains > kMaxDomains) return false;
     if (o.link_order != 0 && o.link_order != 1) return false;
-    if (o.schedule < 0 || o.schedule >= 32) return false;
+    if (o.schedule < 0 || o.schedule >= 64) return false;
+    if ((o.schedule & 32) && o.domains > 1) return false;   // the giant-component skip has no domain mode
     if (o.compression != 0 && o.compression != 1) return false;
     for (int k = 0; k < 2; ++k)
         if (o.reserved[k] != 0) return false;
@@ -317,7 +318,8 @@ fof_status make_layout(const fof_options &o, int64_t n_total, int64_t cells, int
     p.o_part = take(sizeof(int32_t) * (size_t)p.scan_tiles);
     p.o_kmap = take(sizeof(int32_t) * n);
     p.o_sorted = take(sizeof(float) * 4 * n);
-    p.o_perm = take(sizeof(int32_t) * 2 * n);
+    p.o_orig = take(sizeof(int32_t) * n);
+    p.o_gmin = take(sizeof(int32_t) * n);
     p.o_parent = take(sizeof(int32_t) * n);
     p.o_gsize = take(sizeof(int32_t) * n);
     p.max_items = fof::max_dense_items(n_total, dense_min_of(o));
@@ -401,6 +403,8 @@ void carve(const fof_options &o, const Layout &p, const BoxDev &box0, void *ws, 
     d.dense_blocks = dense_grid[(o.schedule >> 2) & 3];
     d.premerge = (o.schedule & 16) ? 0 : 1;
     d.find_mode = o.compression;
+    d.giant_skip = (o.schedule & 32) ? 1 : 0;
+    d.sample = 0;
     d.domains = o.domains > 1 ? o.domains : 0;
     d.link_random = o.link_order == 1 ? 1 : 0;
     d.max_items = p.max_items;
@@ -414,7 +418,8 @@ void carve(const fof_options &o, const Layout &p, const BoxDev &box0, void *ws, 
     d.scan_part = at<int32_t>(ws, p.o_part);
     d.kmap = at<int32_t>(ws, p.o_kmap);
     d.sorted = at<float4>(ws, p.o_sorted);
-    d.perm = at<int2>(ws, p.o_perm);
+    d.orig = at<int32_t>(ws, p.o_orig);
+    d.gmin = at<int32_t>(ws, p.o_gmin);
     d.parent = at<int32_t>(ws, p.o_parent);
     d.gsize = at<int32_t>(ws, p.o_gsize);
     d.items = at<int4>(ws, p.o_items);

@@ -162,6 +162,38 @@ __device__ __forceinline__ int find_root(int *parent, int x, int mode, bool rand
     return mode == 1 ? find_depth2(parent, x, random) : find_halve(parent, x);
 }
 
+// Roots of the kN nodes x[] by path halving, advanced in lockstep: every
+// round issues the loads of all nodes still searching together, so their
+// latencies overlap instead of adding up. Every x[v] is a valid node, so the
+// loads need no guard; nodes already at their root just repeat a load.
+template <int kN>
+__device__ __forceinline__ void find_many(int *parent, int (&x)[kN], bool (&done)[kN])
+{
+    while (true) {
+        int px[kN], gx[kN];
+#pragma unroll
+        for (int v = 0; v < kN; ++v) px[v] = ld_rel(parent + x[v]);
+#pragma unroll
+        for (int v = 0; v < kN; ++v) done[v] = done[v] || px[v] == x[v];
+#pragma unroll
+        for (int v = 0; v < kN; ++v) gx[v] = ld_rel(parent + px[v]);
+        bool any = false;
+#pragma unroll
+        for (int v = 0; v < kN; ++v) {
+            if (done[v]) continue;
+            if (gx[v] == px[v]) {
+                x[v] = px[v];
+                done[v] = true;
+            } else {
+                st_rel(parent + x[v], gx[v]);
+                x[v] = gx[v];
+                any = true;
+            }
+        }
+        if (!any) return;
+    }
+}
+
 // Merge the groups of a and b: hook the root of lower priority under the other
 // with a compare-and-swap that expects it to still be a root. On failure the
 // CAS returns the node's new parent, and the search continues from there.

@@ -41,6 +41,7 @@ struct Counters {
     unsigned int n_boundary;    // domain mode: linked pairs across domains (may exceed the list's capacity)
     unsigned int n_bgroups;     // domain mode: distinct local groups met by those pairs
     unsigned int depth_max;     // stats: longest path to a root before the flatten
+    int giant;                  // giant-component skip: a node of the largest group in the sample
     unsigned long long depth_sum;   // stats: sum of those path lengths
 };
 
@@ -66,6 +67,9 @@ struct Plan {
     int32_t link_random;    // 1: roots hook by a pseudo-random priority of the index, not the index
     int32_t premerge;       // 1: dense cells are pre-merged by sub-cells before the wavefront search
     int32_t find_mode;      // 0: finds halve paths; 1: a path of length >= 2 is compressed onto its root
+    int32_t giant_skip;     // 1: Afforest-style linking (sampled axis links, then the rest skipping the
+                            // largest group found)
+    int32_t sample;         // set for the first pass of giant_skip: axis-neighbour cells only
     int64_t max_items;      // capacity of `items`
     int64_t max_edges;      // capacity of `edges`: kEdgeSlices slices of max_edges / kEdgeSlices
 
@@ -92,7 +96,8 @@ struct Plan {
     int64_t n_waves;
     int32_t *kmap;          // [n] staging slot of each sorted slot
     float4 *sorted;         // [n] cell-sorted x, y, z
-    int2 *perm;             // [n] .x original index of sorted particle s, .y group minimum (at roots)
+    int32_t *orig;          // [n] original index of sorted particle s
+    int32_t *gmin;          // [n] smallest original index of the group, at its root
     int32_t *parent;        // [n] union-find forest over sorted indices
     int32_t *gsize;         // [n] group member count at roots (sorted indices)
     int4 *items;            // [max_items] dense work: {cell, first home particle, box, 0}

@@ -74,6 +74,7 @@ __global__ void __launch_bounds__(kBlock) k_clear(Plan p)
         p.counters->n_bgroups = 0;
         p.counters->depth_max = 0;
         p.counters->depth_sum = 0;
+        p.counters->giant = 0;
     }
 }
 
@@ -567,7 +568,8 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
                 const int dst = a + local;
                 const int i = __float_as_int(v.w);
                 p.sorted[dst] = make_float4(v.x, v.y, v.z, 0.0f);
-                p.perm[dst] = make_int2(i, i);
+                p.orig[dst] = i;
+                p.gmin[dst] = i;
                 p.parent[dst] = dst;
                 p.gsize[dst] = 1;
                 p.kmap[dst] = p.stage2_k[k];
@@ -602,7 +604,8 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
                 const int dst = a + d0 + q * kSegBlock;
                 const int i = __float_as_int(v[q].w);
                 p.sorted[dst] = make_float4(v[q].x, v[q].y, v[q].z, 0.0f);
-                p.perm[dst] = make_int2(i, i);
+                p.orig[dst] = i;
+                p.gmin[dst] = i;
                 p.parent[dst] = dst;
                 p.gsize[dst] = 1;
                 p.kmap[dst] = k_of[q];
@@ -659,7 +662,7 @@ __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
             if (r != s) {
                 p.parent[s] = r;
                 root_key = r;
-                m = p.perm[s].x;
+                m = p.orig[s];
                 c = 1;
             }
         }
@@ -675,13 +678,13 @@ __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
                     c += pend_c;
                 }
             } else if (lane == 0) {
-                atomicMin(&p.perm[pend_key].y, pend_m);
+                atomicMin(&p.gmin[pend_key], pend_m);
                 atomicAdd(&p.gsize[pend_key], pend_c);
             }
         }
         const int lm = __shfl(m, last_head, 64), lc = __shfl(c, last_head, 64);
         if (head && lane != last_head) {
-            atomicMin(&p.perm[root_key].y, m);
+            atomicMin(&p.gmin[root_key], m);
             atomicAdd(&p.gsize[root_key], c);
         }
         pend_key = key_last;
@@ -689,7 +692,7 @@ __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
         pend_c = lc;
     }
     if (pend_key >= 0 && lane == 0) {
-        atomicMin(&p.perm[pend_key].y, pend_m);
+        atomicMin(&p.gmin[pend_key], pend_m);
         atomicAdd(&p.gsize[pend_key], pend_c);
     }
 }
@@ -711,9 +714,8 @@ __device__ __forceinline__ void resolve_tile(const Plan &p, int64_t s64)
         const int s = (int)s64;
         b = p.n_boxes == 1 ? 0 : find_box_wave(p.box_p0, p.n_boxes, s64);
         const int r = p.parent[s];
-        const int o = p.perm[s].x;
-        const int2 pr = p.perm[r];
-        const int m = pr.y;
+        const int o = p.orig[s];
+        const int m = p.gmin[r];
         const int p0 = p.n_boxes == 1 ? 0 : (int)p.box_p0[b];
         staged[p.kmap[s]] = make_int2(m - p0, (o == m) ? p.gsize[r] : 0);
         root = r == s;
@@ -796,7 +798,7 @@ __global__ void __launch_bounds__(kBlock) k_relink_reset(Plan p)
     for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < p.n; s += stride) {
         p.parent[s] = (int)s;
         p.gsize[s] = 1;
-        p.perm[s].y = p.perm[s].x;
+        p.gmin[s] = p.orig[s];
     }
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < p.n_boxes) p.n_groups[t] = 0;

@@ -465,7 +465,16 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
                 }
                 const int xcode[3] = {cx == 0 ? 1 : 0, 0, cx + 1 == nc ? 2 : 0};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) add_row(R, st[r], en[r], xcode, yz[r], dense_min);
+                for (int r = 0; r < 4; ++r) {
+                    if (p.sample) {
+                        // the first pass of the giant-component skip: the axis
+                        // neighbours (dy, dz) = (1, 0) and (0, 1), centre cells only
+#pragma unroll
+                        for (int e = 0; e < 3; ++e)
+                            if (!((r == 0 || r == 2) && e == 1)) en[r][e] = st[r][e];
+                    }
+                    add_row(R, st[r], en[r], xcode, yz[r], dense_min);
+                }
             }
         }
         // flatten the units of the wave: unit and pair offsets by prefix sums
@@ -520,11 +529,18 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
     }
 }
 
-// Merges the queued pairs: one thread per pair, no ordering needed. Slice s
-// holds the pairs found on XCD s % 8 (the search's work-group b appends to
-// slice b % 256, and work-groups go to XCDs round-robin), whose home
-// particles are that XCD's contiguous range of cells; its kUnionParts
-// work-groups run on the same XCD, so the finds of a slice stay in one L2.
+constexpr int kUnionIlp = 4;   // queued pairs a lane merges at once
+
+// Merges the queued pairs, no ordering needed. Each lane carries kUnionIlp
+// pairs at once: the finds of their 2 kUnionIlp end points advance together,
+// then each pair whose roots differ hooks the root of lower priority under
+// the other; a compare-and-swap that finds the root moved continues as an
+// ordinary union from the value it returned. Slice s holds the pairs found on
+// XCD s % 8 (the search's work-group b appends to slice b % 256, and
+// work-groups go to XCDs round-robin), whose home particles are that XCD's
+// contiguous range of cells; its kUnionParts work-groups run on the same XCD,
+// so the finds of a slice stay in one L2. Domain mode and the depth-2
+// compression take the plain path, one pair at a time.
 constexpr int kUnionParts = 16;
 static_assert(kEdgeSlices % kXcds == 0, "slices split evenly over the XCDs");
 
@@ -538,10 +554,41 @@ __global__ void __launch_bounds__(kBlock) k_union_edges(Plan p)
     const unsigned fill = p.edge_fill[slice];
     const int64_t ne = (int64_t)fill < cap ? (int64_t)fill : cap;
     const int2 *edges = p.edges + slice * cap;
+    const int64_t stride = (int64_t)kUnionParts * kBlock;
     unsigned retries = 0;
-    for (int64_t k = (int64_t)part * kBlock + threadIdx.x; k < ne; k += (int64_t)kUnionParts * kBlock) {
-        const int2 e = edges[k];
-        merge_pair(p, e.x, e.y, retries);
+    if (p.domains > 1 || p.find_mode != 0) {
+        for (int64_t k = (int64_t)part * kBlock + threadIdx.x; k < ne; k += stride) {
+            const int2 e = edges[k];
+            merge_pair(p, e.x, e.y, retries);
+        }
+    } else {
+        const bool rnd = p.link_random != 0;
+        for (int64_t k0 = (int64_t)part * kBlock + threadIdx.x; k0 < ne; k0 += kUnionIlp * stride) {
+            int x[2 * kUnionIlp];
+            bool done[2 * kUnionIlp];
+#pragma unroll
+            for (int u = 0; u < kUnionIlp; ++u) {
+                const int64_t k = k0 + u * stride;
+                const bool in = k < ne;
+                const int2 e = in ? edges[k] : make_int2(0, 0);
+                x[2 * u] = e.x;
+                x[2 * u + 1] = e.y;
+                done[2 * u] = done[2 * u + 1] = !in;
+            }
+            find_many<2 * kUnionIlp>(p.parent, x, done);
+#pragma unroll
+            for (int u = 0; u < kUnionIlp; ++u) {
+                const int a = x[2 * u], b = x[2 * u + 1];
+                if (a == b || k0 + u * stride >= ne) continue;
+                const bool a_first = link_key(a, rnd) < link_key(b, rnd);
+                const int lo = a_first ? a : b;
+                const int hi = a_first ? b : a;
+                int expected = hi;
+                if (!__hip_atomic_compare_exchange_strong(p.parent + hi, &expected, lo, __ATOMIC_RELAXED,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    retries += 1 + unite(p.parent, expected, lo, rnd);
+            }
+        }
     }
     if (kStats) {
         unsigned long long r = wave_sum_u64((unsigned long long)retries);
@@ -552,14 +599,32 @@ __global__ void __launch_bounds__(kBlock) k_union_edges(Plan p)
 }
 
 // ---------------------------------------------------------- dense (wave) --
+//
+// One work item = up to 64 particles of a dense cell, one per lane ("home"
+// particles). Candidates are staged in LDS, 64 at a time, and every staged
+// candidate is tested against all home lanes at once (its LDS address is
+// uniform, so the read is a broadcast). A stage is filled from a list of
+// candidate ranges (the cell itself, or several neighbour cells at once), so
+// that small neighbour cells do not each cost a round of loads:
+//  - the cell itself (only candidates above the home particle count);
+//  - every neighbour cell the item searches (the upper half shell, and the
+//    lower half where the neighbour is sparse) whose periodic image needs no
+//    shift of the home coordinate, together in one list;
+//  - FP32 only: each neighbour reached across a high face of the box, where
+//    the home coordinate is shifted by -L (exact there), on its own.
+// When every home lane knows the same root, candidates of that root are
+// already in their group and are dropped while the stage is filled.
 
 struct StageF {
-    float4 v[64];            // x, y, z (neighbour shift applied), cached root (bits)
+    float4 v[64];            // x, y, z (candidate-side periodic shift applied), cached root (bits)
+    int slot[64];            // sorted slot of the candidate
 };
 
 struct StageD {
     double x[64], y[64], z[64];
+    double sx[64], sy[64], sz[64];   // periodic shift, added after the rounded difference
     int root[64];
+    int slot[64];
 };
 
 template <bool kFP64>
@@ -573,10 +638,22 @@ struct Stage<true> {
     using T = StageD;
 };
 
+// Candidate ranges of one stage fill: range r covers slots
+// [j0[r], j0[r] + pre[r + 1] - pre[r]) with periodic shift code code[r]
+// (bits 0-1, 2-3, 4-5 for x, y, z: 1 = the neighbour is the top cell across
+// the low face, its FP32 coordinate minus L is exact; 2 = the neighbour lies
+// across the high face, handled on the home side in FP32). In double the
+// shift (+L for 1, -L for 2) is added after the rounded difference.
+struct RangeList {
+    int pre[28];
+    int j0[27];
+    int code[27];
+};
+
 // Box parameters the inner loops need, held in registers.
 struct BoxRegs {
     double L, half, l2;
-    float lo32, hi32;
+    float lo32, hi32, L32;
     bool strict;
 };
 
@@ -595,12 +672,12 @@ struct BoxRegs {
 // distance decides anything.
 template <bool kFP64, bool kStats, bool kGeneral>
 __device__ __forceinline__ void dense_hit(const Plan &p, const BoxRegs &br, const typename Stage<kFP64>::T &st,
-                                          int kk, int jb, bool cand, float r, float4 pi, int &root_i, int &known0,
+                                          int kk, bool cand, float r, float4 pi, int &root_i, int &known0,
                                           int &known1, unsigned long long &links, unsigned long long &band,
                                           unsigned &retries)
 {
     if (!cand) return;
-    const int j = jb + kk;
+    const int j = st.slot[kk];
     bool link = true;
     if constexpr (!kFP64) {
         if (!(r < br.lo32)) {
@@ -635,36 +712,40 @@ __device__ __forceinline__ float dist2_f32(const float4 cj, float hx, float hy, 
 }
 
 // The double predicate of the home lane and staged candidate kk, with the
-// neighbour's periodic shift added after the rounded difference.
+// candidate's periodic shift added after the rounded difference.
 __device__ __forceinline__ bool link_f64_staged(const StageD &st, int kk, double dxi, double dyi, double dzi,
-                                                double Lx, double Ly, double Lz, const BoxRegs &br)
+                                                const BoxRegs &br)
 {
-    const double tx = (dxi - st.x[kk]) + Lx;
-    const double ty = (dyi - st.y[kk]) + Ly;
-    const double tz = (dzi - st.z[kk]) + Lz;
+    const double tx = (dxi - st.x[kk]) + st.sx[kk];
+    const double ty = (dyi - st.y[kk]) + st.sy[kk];
+    const double tz = (dzi - st.z[kk]) + st.sz[kk];
     const double sxy = tx * tx + ty * ty;
     const double r2 = sxy + tz * tz;
     return br.strict ? (r2 < br.l2) : (r2 <= br.l2);
 }
 
 // Tests the staged candidates [0, cnt) against the wave's home particles.
-// kSelf: the candidates come from the home cell; only j > i counts. Without
-// statistics a candidate whose cached root is known to be in the home
-// particle's group is dropped together with the distance test's verdict, so
-// once a halo's groups have merged the batch runs without branching.
+// An item of at most 32 (or 16) home particles holds copies of them in both
+// halves (all four quarters) of the wave: lane l is home particle l % H and
+// tests candidate kk + l / H, so one step tests G = 64 / H candidates.
+// kSelf: the candidates come from the home cell; only slots above the home
+// particle's count. Without statistics a candidate whose cached root is
+// known to be in the home particle's group is dropped together with the
+// distance test's verdict.
 template <bool kFP64, bool kStats, bool kGeneral, bool kSelf>
 __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, const typename Stage<kFP64>::T &st,
-                                            int cnt, int jb, int i, bool vi, float4 pi, float hx, float hy,
-                                            float hz, double dxi, double dyi, double dzi, double Lx, double Ly,
-                                            double Lz, int &root_i, int &known0, int &known1,
-                                            unsigned long long &links, unsigned long long &band, unsigned &retries)
+                                            int cnt, int G, int q, int i, bool vi, float4 pi, float hx, float hy,
+                                            float hz, double dxi, double dyi, double dzi, int &root_i, int &known0,
+                                            int &known1, unsigned long long &links, unsigned long long &band,
+                                            unsigned &retries)
 {
-    const int rel = i - jb;   // candidate kk is above the home particle iff kk > rel
     auto fresh = [&](int rj) { return kStats || (rj != root_i && rj != known0); };
     int kk = 0;
     if constexpr (!kFP64) {
-        for (; kk + 4 <= cnt; kk += 4) {
-            const float4 q0 = st.v[kk + 0], q1 = st.v[kk + 1], q2 = st.v[kk + 2], q3 = st.v[kk + 3];
+        const int G4 = 4 * G;
+        for (; kk + G4 <= cnt; kk += G4) {
+            const int k0 = kk + q, k1 = k0 + G, k2 = k1 + G, k3 = k2 + G;
+            const float4 q0 = st.v[k0], q1 = st.v[k1], q2 = st.v[k2], q3 = st.v[k3];
             const float r0 = dist2_f32(q0, hx, hy, hz);
             const float r1 = dist2_f32(q1, hx, hy, hz);
             const float r2 = dist2_f32(q2, hx, hy, hz);
@@ -674,38 +755,118 @@ __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, co
             bool c2 = r2 <= br.hi32 && fresh(__float_as_int(q2.w));
             bool c3 = r3 <= br.hi32 && fresh(__float_as_int(q3.w));
             if constexpr (kSelf) {
-                c0 = c0 && kk + 0 > rel;
-                c1 = c1 && kk + 1 > rel;
-                c2 = c2 && kk + 2 > rel;
-                c3 = c3 && kk + 3 > rel;
+                c0 = c0 && st.slot[k0] > i;
+                c1 = c1 && st.slot[k1] > i;
+                c2 = c2 && st.slot[k2] > i;
+                c3 = c3 && st.slot[k3] > i;
             }
             if (__ballot(c0 || c1 || c2 || c3)) {
-                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 0, jb, c0, r0, pi, root_i, known0, known1, links,
-                                                   band, retries);
-                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 1, jb, c1, r1, pi, root_i, known0, known1, links,
-                                                   band, retries);
-                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 2, jb, c2, r2, pi, root_i, known0, known1, links,
-                                                   band, retries);
-                dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk + 3, jb, c3, r3, pi, root_i, known0, known1, links,
-                                                   band, retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, k0, c0, r0, pi, root_i, known0, known1, links, band,
+                                                   retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, k1, c1, r1, pi, root_i, known0, known1, links, band,
+                                                   retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, k2, c2, r2, pi, root_i, known0, known1, links, band,
+                                                   retries);
+                dense_hit<kFP64, kStats, kGeneral>(p, br, st, k3, c3, r3, pi, root_i, known0, known1, links, band,
+                                                   retries);
             }
         }
     }
-    for (; kk < cnt; ++kk) {
+    for (; kk < cnt; kk += G) {
+        const int k = kk + q;
+        const bool in = k < cnt;
+        const int kr = in ? k : 0;   // a valid stage entry for lanes past the end
         bool c;
         float r = 0.f;
         if constexpr (kFP64) {
-            c = vi && fresh(st.root[kk]) && link_f64_staged(st, kk, dxi, dyi, dzi, Lx, Ly, Lz, br);
+            c = in && vi && fresh(st.root[kr]) && link_f64_staged(st, kr, dxi, dyi, dzi, br);
         } else {
-            const float4 q = st.v[kk];
-            r = dist2_f32(q, hx, hy, hz);
-            c = r <= br.hi32 && fresh(__float_as_int(q.w));   // false for invalid (NaN) lanes and candidates
+            const float4 cq = st.v[kr];
+            r = dist2_f32(cq, hx, hy, hz);
+            c = in && r <= br.hi32 && fresh(__float_as_int(cq.w));   // false for invalid (NaN) lanes
         }
-        if constexpr (kSelf) c = c && kk > rel;
+        if constexpr (kSelf) c = c && st.slot[kr] > i;
         if (__ballot(c))
-            dense_hit<kFP64, kStats, kGeneral>(p, br, st, kk, jb, c, r, pi, root_i, known0, known1, links, band,
-                                               retries);
+            dense_hit<kFP64, kStats, kGeneral>(p, br, st, kr, c, r, pi, root_i, known0, known1, links, band, retries);
     }
+}
+
+// Fills stages from the ranges in `rl` (lane l < 27 holds range l's length
+// in `len`, its first slot in `j0`, its shift code in `code`) and tests them
+// against the home lanes (home coordinates hx, hy, hz, already shifted where
+// the group needs it).
+template <bool kFP64, bool kStats, bool kGeneral, bool kSelf>
+__device__ __forceinline__ void dense_ranges(const Plan &p, const BoxRegs &br, typename Stage<kFP64>::T &st,
+                                             RangeList &rl, int len, int j0, int code, int G, int q, int i, bool vi,
+                                             float4 pi, float hx, float hy, float hz, int n_home, int &root_i,
+                                             int &known0,
+                                             int &known1, unsigned long long &tests, unsigned long long &links,
+                                             unsigned long long &band, unsigned &retries)
+{
+    const int lane = lane_id();
+    const int incl = wave_incl_scan(lane < 27 ? len : 0);
+    const int total = __shfl(incl, 63, 64);
+    if (total == 0) return;
+    if (lane < 27) {
+        rl.pre[lane + 1] = incl;
+        rl.j0[lane] = j0;
+        rl.code[lane] = code;
+    }
+    if (lane == 0) rl.pre[0] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const bool rnd = kGeneral && p.link_random;
+    const double dxi = (double)pi.x, dyi = (double)pi.y, dzi = (double)pi.z;
+#pragma unroll 1
+    for (int t0 = 0; t0 < total; t0 += 64) {
+        const int t = t0 + lane;
+        const bool vj = t < total;
+        int r = 0;
+        if (vj) {
+#pragma unroll
+            for (int step = 16; step > 0; step >>= 1)
+                if (r + step < 27 && rl.pre[r + step] <= t) r += step;
+        }
+        const int j = vj ? rl.j0[r] + (t - rl.pre[r]) : 0;
+        const int cj = vj ? rl.code[r] : 0;
+        const float4 cq = vj ? p.sorted[j] : make_float4(qnan(), qnan(), qnan(), 0.f);
+        // the home particle's cached root, checked once per stage fill
+        // (other waves may have merged its group meanwhile)
+        const int pr = (!kStats && t0 == 0 && vi) ? ld_rel(p.parent + root_i) : root_i;
+        const int rj = vj ? find_root(p.parent, j, p.find_mode, rnd) : -2;
+        bool keep = vj;
+        if constexpr (!kStats) {
+            if (pr != root_i) root_i = find_root(p.parent, pr, p.find_mode, rnd);
+            // one root for every home lane: candidates of that root are in its group
+            const int rh = __builtin_amdgcn_readfirstlane(root_i);   // lane 0 is a home particle
+            if (__ballot(vi && root_i != rh) == 0) keep = keep && rj != rh;
+        }
+        const unsigned long long km = __ballot(keep);
+        const int cnt = __popcll(km);
+        if (kStats) tests += (unsigned long long)min(64, total - t0) * (unsigned long long)n_home;
+        if (cnt == 0) continue;
+        __builtin_amdgcn_wave_barrier();   // the previous stage has been read
+        if (keep) {
+            const int at = __builtin_amdgcn_mbcnt_hi((unsigned)(km >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)km, 0u));
+            st.slot[at] = j;
+            if constexpr (kFP64) {
+                st.x[at] = (double)cq.x;
+                st.y[at] = (double)cq.y;
+                st.z[at] = (double)cq.z;
+                st.sx[at] = axis_shift(cj & 3, br.L);
+                st.sy[at] = axis_shift((cj >> 2) & 3, br.L);
+                st.sz[at] = axis_shift((cj >> 4) & 3, br.L);
+                st.root[at] = rj;
+            } else {
+                st.v[at] = make_float4((cj & 3) == 1 ? cq.x - br.L32 : cq.x,
+                                       ((cj >> 2) & 3) == 1 ? cq.y - br.L32 : cq.y,
+                                       ((cj >> 4) & 3) == 1 ? cq.z - br.L32 : cq.z, __int_as_float(rj));
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        dense_batch<kFP64, kStats, kGeneral, kSelf>(p, br, st, cnt, G, q, i, vi, pi, hx, hy, hz, dxi, dyi, dzi,
+                                                    root_i, known0, known1, links, band, retries);
+    }
+    __builtin_amdgcn_wave_barrier();   // rl and the stage are reused by the next call
 }
 
 template <bool kFP64, bool kStats, bool kGeneral>
@@ -713,8 +874,10 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
 {
     using StageT = typename Stage<kFP64>::T;
     __shared__ StageT stage[kWaves];
+    __shared__ RangeList ranges[kWaves];
     const int wid = threadIdx.x >> 6, lane = lane_id();
     StageT &st = stage[wid];
+    RangeList &rl = ranges[wid];
     unsigned long long tests = 0, links = 0, band = 0;
     unsigned retries = 0;
     const int n_items = (int)p.counters->n_items;
@@ -732,89 +895,62 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
         br.l2 = bd.l2;
         br.lo32 = bd.lo32;
         br.hi32 = bd.hi32;
+        br.L32 = bd.L32;
         br.strict = p.strict != 0;
-        const float L32 = bd.L32;
         const int local = c - cb;
         const int cx = local % nc, cy = (local / nc) % nc, cz = local / (nc * nc);
-        // the slots of the 27 neighbour cells, one cell per lane (lanes 0-26,
-        // neighbour nb = 9 (dz + 1) + 3 (dy + 1) + dx + 1), all looked up at once
-        int nb_j0 = 0, nb_j1 = 0;
+        // the 27 neighbour cells, one per lane (lanes 0-26, neighbour
+        // nb = 9 (dz + 1) + 3 (dy + 1) + dx + 1), looked up at once; code:
+        // per axis 1 = the neighbour is the top cell across the low face,
+        // 2 = the home cell is the top one and the neighbour across the high face
+        int nb_j0 = 0, nb_j1 = 0, code = 0;
         if (lane < 27) {
             int nx = cx + lane % 3 - 1, ny = cy + (lane / 3) % 3 - 1, nz = cz + lane / 9 - 1;
-            nx += nx < 0 ? nc : (nx >= nc ? -nc : 0);
-            ny += ny < 0 ? nc : (ny >= nc ? -nc : 0);
-            nz += nz < 0 ? nc : (nz >= nc ? -nc : 0);
+            if (nx < 0) { nx += nc; code |= 1; } else if (nx >= nc) { nx -= nc; code |= 2; }
+            if (ny < 0) { ny += nc; code |= 1 << 2; } else if (ny >= nc) { ny -= nc; code |= 2 << 2; }
+            if (nz < 0) { nz += nc; code |= 1 << 4; } else if (nz >= nc) { nz -= nc; code |= 2 << 4; }
             const int2 sp = cell_span(p, cb + (nz * nc + ny) * nc + nx);
             nb_j0 = sp.x;
             nb_j1 = sp.y;
         }
         const int ce = __shfl(nb_j1, 13, 64);   // the cell itself
-        const int i = first + lane;
+        const int n_home = min(64, ce - first);
+        // home particles per copy (H) and copies (G = 64 / H)
+        const int H = n_home > 32 ? 64 : (n_home > 16 ? 32 : 16);
+        const int G = 64 / H, q = lane / H;
+        const int i = first + (lane & (H - 1));
         const bool vi = i < ce;
         const float4 pi = vi ? p.sorted[i] : make_float4(qnan(), qnan(), qnan(), 0.f);
-        const bool rnd = kGeneral && p.link_random;
-        const int mode = p.find_mode;
-        int root_i = vi ? find_root(p.parent, i, mode, rnd) : -1;
+        int root_i = vi ? find_root(p.parent, i, p.find_mode, kGeneral && p.link_random) : -1;
         int known0 = -3, known1 = -3;   // never a node
-        const double dxi = (double)pi.x, dyi = (double)pi.y, dzi = (double)pi.z;
-        const int n_home = min(64, ce - first);
+        // neighbours searched from here: the upper half shell, and the lower
+        // half where the neighbour is sparse (a dense one searches the pair)
+        const int nlen = nb_j1 - nb_j0;
+        const bool searched = lane < 27 && lane != 13 && nlen > 0 && (lane > 13 || nlen < p.dense_min);
+        const bool home_shift = (code & 0x2a) != 0;   // some axis has code 2
+        const bool together = searched && (kFP64 || !home_shift);
 
-#pragma unroll 1
-        for (int nb = 0; nb < 27; ++nb) {
-            const int dz = nb / 9 - 1, dy = (nb / 3) % 3 - 1, dx = nb % 3 - 1;
-            const bool self = nb == 13;
-            const bool upper = nb > 13;
-            int nx = cx + dx, ny = cy + dy, nz = cz + dz;
-            float hx = pi.x, hy = pi.y, hz = pi.z, sx = 0.f, sy = 0.f, sz = 0.f;
-            double Lx = 0.0, Ly = 0.0, Lz = 0.0;
-            if (nx < 0) { nx += nc; sx = L32; Lx = br.L; }
-            else if (nx >= nc) { nx -= nc; hx = pi.x - L32; Lx = -br.L; }
-            if (ny < 0) { ny += nc; sy = L32; Ly = br.L; }
-            else if (ny >= nc) { ny -= nc; hy = pi.y - L32; Ly = -br.L; }
-            if (nz < 0) { nz += nc; sz = L32; Lz = br.L; }
-            else if (nz >= nc) { nz -= nc; hz = pi.z - L32; Lz = -br.L; }
-            int j0 = __builtin_amdgcn_readfirstlane(__shfl(nb_j0, nb, 64));
-            const int j1 = __builtin_amdgcn_readfirstlane(__shfl(nb_j1, nb, 64));
-            if (self) j0 = first;
-            else if (!upper && j1 - j0 >= p.dense_min) continue;   // that dense cell searches this pair
-#pragma unroll 1
-            for (int jb = j0; jb < j1; jb += 64) {
-                const int j = jb + lane;
-                const bool vj = j < j1;
-                const float4 q = vj ? p.sorted[j] : make_float4(qnan(), qnan(), qnan(), 0.f);
-                // the home particle's cached root, checked once per neighbour
-                // cell (other waves may have merged its group meanwhile)
-                const int pr = (!kStats && jb == j0 && vi) ? ld_rel(p.parent + root_i) : root_i;
-                const int rj = vj ? find_root(p.parent, j, mode, rnd) : -2;
-                if constexpr (!kStats) {
-                    if (pr != root_i) root_i = find_root(p.parent, pr, mode, rnd);
-                    // a batch whose candidates all have one root that every
-                    // home particle knows as its own group needs no test
-                    const int r0 = __builtin_amdgcn_readfirstlane(rj);   // lane 0 holds a candidate
-                    if (__ballot(vj && rj != r0) == 0 &&
-                        __ballot(vi && root_i != r0 && known0 != r0 && known1 != r0) == 0)
-                        continue;
-                }
-                if constexpr (kFP64) {
-                    st.x[lane] = (double)q.x;
-                    st.y[lane] = (double)q.y;
-                    st.z[lane] = (double)q.z;
-                    st.root[lane] = rj;
-                } else {
-                    st.v[lane] = make_float4(q.x - sx, q.y - sy, q.z - sz, __int_as_float(rj));
-                }
-                __builtin_amdgcn_wave_barrier();
-                const int cnt = min(64, j1 - jb);
-                if (kStats) tests += (unsigned long long)cnt * (unsigned long long)n_home;
-                if (self)
-                    dense_batch<kFP64, kStats, kGeneral, true>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi,
-                                                               dzi, Lx, Ly, Lz, root_i, known0, known1, links, band,
-                                                               retries);
-                else
-                    dense_batch<kFP64, kStats, kGeneral, false>(p, br, st, cnt, jb, i, vi, pi, hx, hy, hz, dxi, dyi,
-                                                                dzi, Lx, Ly, Lz, root_i, known0, known1, links, band,
-                                                                retries);
-                __builtin_amdgcn_wave_barrier();
+        // the cell itself
+        dense_ranges<kFP64, kStats, kGeneral, true>(p, br, st, rl, lane == 13 ? ce - first : 0, first, 0, G, q, i, vi,
+                                                    pi, pi.x, pi.y, pi.z, n_home, root_i, known0, known1, tests, links,
+                                                    band, retries);
+        // every neighbour that needs no shift of the home coordinate, at once
+        dense_ranges<kFP64, kStats, kGeneral, false>(p, br, st, rl, together ? nlen : 0, nb_j0, code, G, q, i, vi,
+                                                     pi, pi.x, pi.y, pi.z, n_home, root_i, known0, known1, tests,
+                                                     links, band, retries);
+        if constexpr (!kFP64) {
+            // neighbours across a high face, one at a time
+            unsigned long long rest = __ballot(searched && !together);
+            while (rest) {
+                const int nb = __ffsll((long long)rest) - 1;
+                rest &= rest - 1;
+                const int cd = __shfl(code, nb, 64);
+                const float hx = (cd & 3) == 2 ? pi.x - br.L32 : pi.x;
+                const float hy = ((cd >> 2) & 3) == 2 ? pi.y - br.L32 : pi.y;
+                const float hz = ((cd >> 4) & 3) == 2 ? pi.z - br.L32 : pi.z;
+                dense_ranges<kFP64, kStats, kGeneral, false>(p, br, st, rl, lane == nb ? nlen : 0, nb_j0, code, G, q,
+                                                             i, vi, pi, hx, hy, hz, n_home, root_i, known0, known1,
+                                                             tests, links, band, retries);
             }
         }
     }
@@ -963,13 +1099,189 @@ __global__ void __launch_bounds__(kBlock) k_gm_apply(Plan p)
     }
 }
 
+// ------------------------------------------------- giant-component skip --
+// In the manner of Afforest (Sutton et al., IPDPS 2018): after a first pass
+// that links every particle to its axis-neighbour cells only (the per-particle
+// search with Plan::sample set) and the dense-cell search, the largest group
+// of a sample of roots is taken as "giant". The rest of the links is then
+// searched over the whole periodic shell, both ways, but only from particles
+// outside the giant group: a pair with one end inside is found from the other
+// end, and a pair with both ends inside needs no union. Every linked pair of
+// sparse cells is thereby merged; dense cells keep their own search.
+
+__global__ void __launch_bounds__(kBlock) k_edge_reset(Plan p)
+{
+    if (threadIdx.x < kEdgeSlices) p.edge_fill[threadIdx.x] = 0;
+}
+
+constexpr int kGiantSamples = 4096;
+constexpr int kGiantBlock = 1024;
+
+// One work-group: the roots of kGiantSamples evenly spaced particles, sorted
+// in LDS (bitonic), and the value of the longest run of equal roots.
+__global__ void __launch_bounds__(kGiantBlock) k_giant(Plan p)
+{
+    __shared__ int r[kGiantSamples];
+    __shared__ unsigned long long best;
+    const int tid = (int)threadIdx.x;
+    const bool rnd = p.link_random != 0;
+    for (int k = tid; k < kGiantSamples; k += kGiantBlock)
+        r[k] = find_root(p.parent, (int)((int64_t)k * p.n / kGiantSamples), p.find_mode, rnd);
+    if (tid == 0) best = 0;
+    __syncthreads();
+    for (int k = 2; k <= kGiantSamples; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int idx = tid; idx < kGiantSamples; idx += kGiantBlock) {
+                const int ixj = idx ^ j;
+                if (ixj > idx) {
+                    const int a = r[idx], b = r[ixj];
+                    if ((a > b) == ((idx & k) == 0)) {
+                        r[idx] = b;
+                        r[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int idx = tid; idx < kGiantSamples; idx += kGiantBlock) {
+        if (idx > 0 && r[idx - 1] == r[idx]) continue;   // not the start of a run
+        int lo = idx, hi = kGiantSamples;                 // first entry above r[idx]
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (r[mid] <= r[idx]) lo = mid + 1;
+            else hi = mid;
+        }
+        atomicMax(&best, ((unsigned long long)(lo - idx) << 32) | (unsigned)r[idx]);
+    }
+    __syncthreads();
+    if (tid == 0) p.counters->giant = (int)(unsigned)(best & 0xffffffffull);
+}
+
+// The pair test of the per-particle search: FP32 with the image shift applied
+// where it is exact (shift codes as for candidate ranges), re-decided in
+// double inside the band; or the double predicate with the shift added after
+// the rounded difference.
+template <bool kFP64, bool kStats>
+__device__ __forceinline__ bool pair_link(const float4 h, const float4 c, int code, const BoxPair &bx, bool strict,
+                                          unsigned long long &band)
+{
+    if constexpr (kFP64) {
+        const double tx = ((double)h.x - (double)c.x) + axis_shift(code & 3, bx.L);
+        const double ty = ((double)h.y - (double)c.y) + axis_shift((code >> 2) & 3, bx.L);
+        const double tz = ((double)h.z - (double)c.z) + axis_shift((code >> 4) & 3, bx.L);
+        const double sxy = tx * tx + ty * ty;
+        const double r2 = sxy + tz * tz;
+        return strict ? (r2 < bx.l2) : (r2 <= bx.l2);
+    } else {
+        const float dx = axis_diff(h.x, c.x, code & 3, bx.L32);
+        const float dy = axis_diff(h.y, c.y, (code >> 2) & 3, bx.L32);
+        const float dz = axis_diff(h.z, c.z, (code >> 4) & 3, bx.L32);
+        const float rr = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        if (rr < bx.lo32) return true;
+        if (rr > bx.hi32) return false;
+        if (kStats) ++band;
+        return link_fp64(h.x, h.y, h.z, c.x, c.y, c.z, bx.L, bx.half, bx.l2, strict);
+    }
+}
+
+// The second pass: one home particle per lane, skipped when it lies in the
+// giant group or in a dense cell; otherwise every sparse cell of its periodic
+// shell (all 27, both ways, the home particle itself excluded), each cell's
+// candidates in lockstep over the wave so that the edge sink is reached by
+// every lane together.
+template <bool kFP64, bool kStats>
+__global__ void __launch_bounds__(kBlock) k_link_rest(Plan p)
+{
+    __shared__ int2 ebuf[kWaves][kEdgeBuf];
+    const int wid = threadIdx.x >> 6, lane = lane_id();
+    EdgeSink sink{ebuf[wid], 0};
+    unsigned long long tests = 0, links = 0, band = 0;
+    unsigned retries = 0;
+    const bool rnd = p.link_random != 0;
+    const bool strict = p.strict != 0;
+    const int64_t n_tiles = (p.n + 63) / 64;
+    const XcdRange xr = xcd_range(n_tiles, kWaves, wid);
+    for (int64_t tile = xr.first; tile < xr.end; tile += xr.stride) {
+        const int64_t s64 = tile * 64 + lane;
+        bool active = s64 < p.n;
+        const int s = active ? (int)s64 : 0;
+        const int g = find_root(p.parent, p.counters->giant, p.find_mode, rnd);
+        if (active) active = find_root(p.parent, s, p.find_mode, rnd) != g;
+        int b = 0, cx = 0, cy = 0, cz = 0, nc = 3, cb = 0;
+        float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+        BoxPair bx{};
+        if (active) {
+            b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, s);
+            const BoxDev &bd = box_of(p, b);
+            bx = BoxPair::of(bd);
+            h = p.sorted[s];
+            nc = bd.nc;
+            cb = (int)bd.cell_base;
+            cx = cell_coord(h.x, bd.inv_h, nc);
+            cy = cell_coord(h.y, bd.inv_h, nc);
+            cz = cell_coord(h.z, bd.inv_h, nc);
+            const int2 own = cell_span(p, cb + (cz * nc + cy) * nc + cx);
+            if (own.y - own.x >= p.dense_min) active = false;   // the dense search covers its pairs
+        }
+        if (__ballot(active) == 0) continue;
+#pragma unroll 1
+        for (int nb = 0; nb < 27; ++nb) {
+            int j0 = 0, len = 0, code = 0;
+            if (active) {
+                int nx = cx + nb % 3 - 1, ny = cy + (nb / 3) % 3 - 1, nz = cz + nb / 9 - 1;
+                if (nx < 0) { nx += nc; code |= 1; } else if (nx >= nc) { nx -= nc; code |= 2; }
+                if (ny < 0) { ny += nc; code |= 1 << 2; } else if (ny >= nc) { ny -= nc; code |= 2 << 2; }
+                if (nz < 0) { nz += nc; code |= 1 << 4; } else if (nz >= nc) { nz -= nc; code |= 2 << 4; }
+                const int2 sp = cell_span(p, cb + (nz * nc + ny) * nc + nx);
+                if (sp.y - sp.x < p.dense_min) {
+                    j0 = sp.x;
+                    len = sp.y - sp.x;
+                }
+            }
+            int most = len;
+            for (int d = 32; d >= 1; d >>= 1) most = max(most, __shfl_xor(most, d, 64));
+            for (int t = 0; t < most; ++t) {
+                const int j = j0 + t;
+                const bool valid = t < len && j != s;
+                bool link = false;
+                if (valid) {
+                    const float4 c = p.sorted[j];
+                    link = pair_link<kFP64, kStats>(h, c, code, bx, strict, band);
+                    if (kStats) {
+                        ++tests;
+                        if (link) ++links;
+                    }
+                }
+                sink.push(p, link, s, j, retries);
+            }
+        }
+    }
+    sink.flush(p, retries);
+    if (kStats) {
+        tests = wave_sum_u64(tests);
+        links = wave_sum_u64(links);
+        band = wave_sum_u64(band);
+        unsigned long long r = wave_sum_u64((unsigned long long)retries);
+        if (lane == 0) {
+            atomicAdd(&p.counters->sparse_tests, tests);
+            atomicAdd(&p.counters->pair_tests, tests);
+            atomicAdd(&p.counters->links, links);
+            atomicAdd(&p.counters->band_hits, band);
+            atomicAdd(&p.counters->cas_retries, r);
+        }
+    }
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <bool kFP64, bool kStats>
 void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
+    Plan first = p;
+    first.sample = p.giant_skip;   // the giant-component skip starts from the axis links
     if (t) t->mark(K_LINK_SPARSE, false, stream);
-    hipLaunchKernelGGL((k_link_sparse<kFP64, kStats>), dim3((unsigned)p.sparse_blocks), dim3(kBlock), 0, stream, p);
+    hipLaunchKernelGGL((k_link_sparse<kFP64, kStats>), dim3((unsigned)p.sparse_blocks), dim3(kBlock), 0, stream,
+                       first);
     if (t) t->mark(K_LINK_SPARSE, true, stream);
     if (t) t->mark(K_UNION_EDGES, false, stream);
     hipLaunchKernelGGL((k_union_edges<kStats>), dim3(kUnionParts * kEdgeSlices), dim3(kBlock), 0, stream, p);
@@ -985,6 +1297,19 @@ void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
         hipLaunchKernelGGL((k_link_dense<kFP64, kStats, false>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0,
                            stream, p);
     if (t) t->mark(K_LINK_DENSE, true, stream);
+    if (p.giant_skip) {
+        // the rest of the sparse pairs, from the particles outside the giant
+        // group (timed with the per-particle search and the union pass)
+        hipLaunchKernelGGL(k_edge_reset, dim3(1), dim3(kBlock), 0, stream, p);
+        hipLaunchKernelGGL(k_giant, dim3(1), dim3(kGiantBlock), 0, stream, p);
+        if (t) t->mark(K_LINK_SPARSE, false, stream);
+        hipLaunchKernelGGL((k_link_rest<kFP64, kStats>), dim3((unsigned)p.sparse_blocks), dim3(kBlock), 0, stream,
+                           p);
+        if (t) t->mark(K_LINK_SPARSE, true, stream);
+        if (t) t->mark(K_UNION_EDGES, false, stream);
+        hipLaunchKernelGGL((k_union_edges<kStats>), dim3(kUnionParts * kEdgeSlices), dim3(kBlock), 0, stream, p);
+        if (t) t->mark(K_UNION_EDGES, true, stream);
+    }
     if (p.domains > 1) {
         // global merge, timed with the union pass
         if (t) t->mark(K_UNION_EDGES, false, stream);

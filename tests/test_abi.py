@@ -62,7 +62,12 @@ def test_create_rejects_bad_options():
     o = fof.fof_default_options()
     o.link_order = 1
     fof.fof_destroy(fof.fof_create(o))
-    for field, bad in (("schedule", 32), ("schedule", -1), ("compression", 2), ("compression", -1)):
+    o = fof.make_options(schedule=fof.schedule_bits(giant_skip=True), domains=4)   # no domain mode with it
+    with pytest.raises(fof.FoFError) as e:
+        fof.fof_create(o)
+    assert e.value.status == fof.FOF_ERR_INVALID_ARG
+    fof.fof_destroy(fof.fof_create(fof.make_options(schedule=fof.schedule_bits(giant_skip=True))))
+    for field, bad in (("schedule", 64), ("schedule", -1), ("compression", 2), ("compression", -1)):
         o = fof.fof_default_options()
         setattr(o, field, bad)
         with pytest.raises(fof.FoFError) as e:
