@@ -147,7 +147,10 @@ typedef struct {
                                 decided in double */
     int32_t sub_cells_per_axis; /* k: dense cells are pre-merged by k^3 sub-cells whose diagonal is
                                 at most l_x (1 - 1e-6); 0 = no pre-merge */
-    int32_t reserved[2];
+    int32_t sub_cells_adjacent; /* 1: the sub-cells are small enough (2 sqrt(3) s <= l_x (1 - 1e-6),
+                                s their side) that any two points of two touching sub-cells are
+                                linked, and touching occupied sub-cells are merged too */
+    int32_t reserved[1];
 } fof_box_info;
 
 /* Re-links the particles of the last successful fof_build_cells with new

@@ -60,7 +60,7 @@ class Stats(ctypes.Structure):
 class BoxInfo(ctypes.Structure):
     _fields_ = [("cells_per_axis", ctypes.c_int64), ("l2", ctypes.c_double), ("lo32", ctypes.c_float),
                 ("hi32", ctypes.c_float), ("fp64_only", ctypes.c_int32), ("sub_cells_per_axis", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("sub_cells_adjacent", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 _lib = None

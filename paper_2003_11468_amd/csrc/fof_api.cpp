@@ -224,16 +224,28 @@ constexpr int kMaxSubK = 10;             // at most 1000 sub-cells per dense cel
 constexpr int kDenseBlocks = 2048;
 constexpr int kSparseBlocks = 1024;
 
-// Sub-cells per cell axis for the pre-merge of dense cells: k sub-cells of
-// side L / (nc k) whose diagonal is at most l_x (1 - 1e-6), so that any two
-// particles in one are linked under both predicates (the margin dwarfs every
-// rounding error of the double predicate and of the sub-cell assignment).
-// 0 (no pre-merge) when more than kMaxSubK would be needed.
-int32_t sub_cells_per_axis(double L, int64_t nc, double lx)
+// Sub-cells per cell axis for the pre-merge of dense cells, and whether they
+// are "adjacent-linked". Points in one sub-cell (side s = L / (nc k)) are at
+// most s sqrt(3) apart, points in two touching sub-cells (across a face, an
+// edge or a corner) less than 2 s sqrt(3). With the smallest k for which
+// 2 s sqrt(3) <= l_x (1 - 1e-6), any two points of touching sub-cells are
+// linked under both predicates (the margin dwarfs every rounding error of the
+// double predicate and of the sub-cell assignment); if that k exceeds
+// kMaxSubK, the smallest k with s sqrt(3) <= l_x (1 - 1e-6) (points of one
+// sub-cell linked); if that exceeds kMaxSubK too, 0 (no pre-merge).
+void sub_cells(double L, int64_t nc, double lx, int32_t *k_out, int32_t *adj_out)
 {
-    const double side = L / (double)nc;
-    const double k = std::ceil(side * std::sqrt(3.0) / (lx * (1.0 - 1e-6)));
-    return (k >= 1.0 && k <= (double)kMaxSubK) ? (int32_t)k : 0;
+    const double side = L / (double)nc, reach = lx * (1.0 - 1e-6);
+    const double k_adj = std::ceil(side * 2.0 * std::sqrt(3.0) / reach);
+    const double k_one = std::ceil(side * std::sqrt(3.0) / reach);
+    *adj_out = 0;
+    *k_out = 0;
+    if (k_adj >= 1.0 && k_adj <= (double)kMaxSubK) {
+        *k_out = (int32_t)k_adj;
+        *adj_out = 1;
+    } else if (k_one >= 1.0 && k_one <= (double)kMaxSubK) {
+        *k_out = (int32_t)k_one;
+    }
 }
 
 int dense_min_of(const fof_options &o) { return o.dense_min > 0 ? o.dense_min : kDefaultDenseMin; }
@@ -255,7 +267,7 @@ fof_status box_geometry(const fof_options &o, int64_t nb, double L, double l, in
     b.inv_h = (double)nc / L;
     b.l2 = l * l;
     fp32_thresholds(b, l);
-    b.sub_k = sub_cells_per_axis(L, nc, l);
+    sub_cells(L, nc, l, &b.sub_k, &b.sub_adj);
     return FOF_OK;
 }
 
@@ -668,7 +680,7 @@ fof_status fof_relink(fof_ctx *ctx, const double *h_lx, int32_t n_boxes)
         const double l = h_lx[k];
         b.l2 = l * l;
         fp32_thresholds(b, l);
-        b.sub_k = sub_cells_per_axis(b.L, b.nc, l);
+        sub_cells(b.L, b.nc, l, &b.sub_k, &b.sub_adj);
         if (ctx->opt.predicate == FOF_PRED_FP32_FILTER && b.use_fp64) ++p.fp64_boxes;
     }
     ctx->dev.box0 = p.boxes[0];
@@ -850,7 +862,7 @@ fof_status fof_describe_box(const fof_options *opt, int64_t n_particles, double 
     out->lo32 = b.lo32;
     out->hi32 = b.hi32;
     out->fp64_only = b.use_fp64;
-    out->sub_cells_per_axis = sub_cells_per_axis(box, nc, lx);
+    sub_cells(box, nc, lx, &out->sub_cells_per_axis, &out->sub_cells_adjacent);
     return FOF_OK;
 }
 

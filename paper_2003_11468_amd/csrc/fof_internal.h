@@ -26,6 +26,7 @@ struct BoxDev {
     float lo32;           // FP32 r2 below this: linked (proven)
     float hi32;           // FP32 r2 above this: not linked (proven)
     int32_t sub_k;        // sub-cells per cell axis whose diagonal is below l_x (0: none used)
+    int32_t sub_adj;      // 1: any two points of two touching sub-cells are linked too
 };
 
 // Device counters (one block of the workspace, cleared by every build).

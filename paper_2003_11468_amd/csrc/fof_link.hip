@@ -968,19 +968,61 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
 }
 
 // Pre-merge of dense cells (before the pair search): one wavefront per dense
-// cell splits it into k^3 sub-cells whose diagonal is below l_x, so any two
-// particles of a sub-cell are linked, and hooks every particle under the
-// lowest particle of its sub-cell. The pair search then meets at most k^3
-// groups per dense cell instead of one per particle, and its cached roots
-// agree far more often. The groups found are unchanged (only linked pairs
-// are merged).
+// cell splits it into k^3 sub-cells small enough that any two particles of
+// one sub-cell are linked, and hooks every particle under the lowest
+// particle of its sub-cell. When the sub-cells are smaller still (sub_adj:
+// any two particles of two sub-cells that touch, across a face, an edge or a
+// corner, are linked), a union-find over the occupied sub-cells in LDS first
+// joins every two touching occupied sub-cells, and each particle is hooked
+// under a particle of its joined set. Only linked pairs (directly or through
+// a chain) are merged, so the groups found are unchanged; the pair search
+// then meets few groups per dense cell, and its staging drops the candidates
+// of the home particles' own group.
 constexpr int kMaxSub = 1000;
+
+__device__ __forceinline__ int lds_ld(int *a) { return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ __forceinline__ void lds_st(int *a, int v)
+{
+    __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Root of sub-cell x in the LDS forest f (path halving; parents only point to
+// smaller indices).
+__device__ __forceinline__ int lds_find(int *f, int x)
+{
+    while (true) {
+        const int px = lds_ld(f + x);
+        if (px == x) return x;
+        const int gx = lds_ld(f + px);
+        if (gx == px) return px;
+        lds_st(f + x, gx);
+        x = gx;
+    }
+}
+
+__device__ __forceinline__ void lds_unite(int *f, int a, int b)
+{
+    while (true) {
+        a = lds_find(f, a);
+        b = lds_find(f, b);
+        if (a == b) return;
+        const int lo = min(a, b), hi = max(a, b);
+        int expected = hi;
+        if (__hip_atomic_compare_exchange_strong(f + hi, &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+        a = expected;
+        b = lo;
+    }
+}
 
 __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
 {
-    __shared__ int rep[kWaves][kMaxSub];
+    __shared__ int rep[kWaves][kMaxSub];    // lowest particle of each sub-cell (INT_MAX: empty)
+    __shared__ int join[kWaves][kMaxSub];   // forest over the sub-cells (sub_adj)
     const int wid = threadIdx.x >> 6, lane = lane_id();
     int *rp = rep[wid];
+    int *jf = join[wid];
     unsigned retries = 0;
     const int n_items = (int)p.counters->n_items;
     const XcdRange xr = xcd_range(n_items, kWaves, wid);
@@ -995,11 +1037,15 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
         const BoxDev &bd = box_of(p, b);
         const int k = bd.sub_k;
         if (k == 0) continue;
+        const bool adj = bd.sub_adj != 0;
         const int ce = __builtin_amdgcn_readfirstlane(sp.y);
         const int nc = bd.nc, local = c - (int)bd.cell_base;
         const int cx = local % nc, cy = (local / nc) % nc, cz = local / (nc * nc);
         const int nsub = k * k * k;
-        for (int t = lane; t < nsub; t += 64) rp[t] = INT_MAX;
+        for (int t = lane; t < nsub; t += 64) {
+            rp[t] = INT_MAX;
+            jf[t] = t;
+        }
         __builtin_amdgcn_wave_barrier();
         auto sub_of = [&](int j) {
             const float4 q = p.sorted[j];
@@ -1012,8 +1058,24 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
         };
         for (int j = cs + lane; j < ce; j += 64) atomicMin(&rp[sub_of(j)], j);
         __builtin_amdgcn_wave_barrier();
+        if (adj) {
+            // join touching occupied sub-cells: each one with the 13 of its
+            // 26 neighbours that come after it
+            for (int t = lane; t < nsub; t += 64) {
+                if (rp[t] == INT_MAX) continue;
+                const int sx = t % k, sy = (t / k) % k, sz = t / (k * k);
+                for (int o = 14; o < 27; ++o) {
+                    const int ux = sx + o % 3 - 1, uy = sy + (o / 3) % 3 - 1, uz = sz + o / 9 - 1;
+                    if (ux < 0 || ux >= k || uy < 0 || uy >= k || uz >= k) continue;
+                    const int u = (uz * k + uy) * k + ux;
+                    if (rp[u] != INT_MAX) lds_unite(jf, t, u);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
         for (int j = cs + lane; j < ce; j += 64) {
-            const int r = rp[sub_of(j)];
+            const int sj = sub_of(j);
+            const int r = rp[adj ? lds_find(jf, sj) : sj];
             if (r != j) retries += unite(p.parent, j, r, p.link_random, p.find_mode);
         }
         __builtin_amdgcn_wave_barrier();

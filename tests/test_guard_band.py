@@ -120,9 +120,12 @@ def test_without_the_band_fp32_alone_would_be_wrong():
 
 
 def test_premerge_sub_cells_are_inside_the_linking_length():
-    """Dense cells are pre-merged by k^3 sub-cells: every two points of one must
-    be linked, so the sub-cell diagonal must stay below l_x with room for the
-    double predicate's rounding; k must be the smallest such count."""
+    """Dense cells are pre-merged by k^3 sub-cells: every two points of one
+    must be linked, and with sub_cells_adjacent every two points of two
+    touching sub-cells too, so the sub-cell diagonal (twice it for touching
+    sub-cells) must stay below l_x with room for the double predicate's
+    rounding; k must be the smallest such count, the touching criterion
+    first."""
     rng = np.random.default_rng(11)
     seen = set()
     for _ in range(400):
@@ -134,20 +137,27 @@ def test_premerge_sub_cells_are_inside_the_linking_length():
             info = fof.fof_describe_box(n, L, lx, fof.make_options(cell_factor=cf))
         except fof.FoFError:
             continue
-        nc, k = info["cells_per_axis"], info["sub_cells_per_axis"]
+        nc, k, adj = info["cells_per_axis"], info["sub_cells_per_axis"], info["sub_cells_adjacent"]
         side = L / nc
-        need = side * np.sqrt(3.0) / (lx * (1 - 1e-6))
+        need_one = side * np.sqrt(3.0) / (lx * (1 - 1e-6))
+        need_adj = 2.0 * need_one
         if k:
             assert 1 <= k <= 10
-            assert side / k * np.sqrt(3.0) <= lx * (1 - 1e-6) * (1 + 1e-12)
-            assert k == int(np.ceil(need))
-            # the FP64 predicate of two points at the far corners of one sub-cell links
-            a = np.zeros(3, dtype=np.float32)
             s = side / k
-            b = np.full(3, s * (1 - 1e-7), dtype=np.float64).astype(np.float32)
+            if adj:
+                assert k == int(np.ceil(need_adj))
+                assert 2.0 * s * np.sqrt(3.0) <= lx * (1 - 1e-6) * (1 + 1e-12)
+                reach = 2.0 * s        # far corners of two sub-cells touching at a corner
+            else:
+                assert need_adj > 10 and k == int(np.ceil(need_one))
+                assert s * np.sqrt(3.0) <= lx * (1 - 1e-6) * (1 + 1e-12)
+                reach = s              # far corners of one sub-cell
+            # the FP64 predicate of two such points links
+            a = np.zeros(3, dtype=np.float32)
+            b = np.full(3, reach * (1 - 1e-7), dtype=np.float64).astype(np.float32)
             t = b.astype(np.float64) - a.astype(np.float64)
             assert float((t[0] * t[0] + t[1] * t[1]) + t[2] * t[2]) < info["l2"]
         else:
-            assert need > 10
-        seen.add(k)
-    assert 0 in seen and len(seen) > 3
+            assert need_one > 10 and adj == 0
+        seen.add((k, adj))
+    assert (0, 0) in seen and any(a for _, a in seen) and any(k and not a for k, a in seen)
