@@ -88,7 +88,7 @@ typedef struct {
                                 stream (read with fof_get_kernel_times) */
     int32_t sort_segment_log2; /* the cell sort takes 2^k consecutive cells per work-group (their
                                 occupancy bits and the counts of the occupied cells in on-chip
-                                memory): k in 6..14; 0 = automatic (about 1.4k particles per
+                                memory): k in 6..16; 0 = automatic (about 1.4k particles per
                                 work-group on average). Changes speed only */
     int32_t domains;         /* > 1: domain-decomposed merge on one GPU (paper, Section 3.3): every box
                                 is cut into this many slabs along x; union-find runs on the links

@@ -286,7 +286,7 @@ fof_status make_layout(const fof_options &o, int64_t n_total, int64_t cells, int
     p.bucket_shift = 0;
     while ((last >> p.bucket_shift) >= 256) ++p.bucket_shift;
     // By default a segment holds about kSegTarget particles on average (its
-    // particles are then placed through LDS), within 2^6 .. 2^14 cells.
+    // particles are then placed through LDS), within 2^6 .. 2^16 cells.
     if (o.sort_segment_log2) {
         p.seg_shift = o.sort_segment_log2;
     } else {

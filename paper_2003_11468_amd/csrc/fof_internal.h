@@ -120,8 +120,8 @@ int64_t sort_tiles_for(int64_t n);
 // Cells per segment of the in-LDS cell sort: 2^kSegLog2Min .. 2^kSegLog2Max;
 // segments per bucket at most 2^kMaxSubLog2.
 constexpr int kSegLog2Min = 6;
-constexpr int kSegLog2Max = 14;
-constexpr int kSegLog2Auto = 14;      // largest segment the automatic choice takes
+constexpr int kSegLog2Max = 16;
+constexpr int kSegLog2Auto = 16;      // largest segment the automatic choice takes
 constexpr int kSegTarget = 1365;      // default: about this many particles per segment
 constexpr int kMaxSubLog2 = 10;
 

@@ -6,7 +6,7 @@
 // The counting sort into cells runs in three levels so that no pass scatters
 // over the whole array and no pass counts cells in global memory. Cells are
 // grouped into at most 256 buckets of consecutive cell indices, and buckets
-// into segments of at most 2^14 cells (a segment's occupancy bits fit in LDS).
+// into segments of at most 2^16 cells (a segment's occupancy bits fit in LDS).
 // Cells are indexed by rank: per 32 cells an occupancy word {bits, rank base},
 // and the first slot of each occupied cell only (no array per cell).
 //   clear          zero the segment counts, group counters and error word
@@ -399,10 +399,14 @@ static_assert(kCntCap >= kOrderCap, "a segment placed through LDS is one window"
 //     written in slot order (coalesced), otherwise written directly.
 // A slot outside [0, P) cannot happen with consistent counts; it is latched
 // as error bit 1 instead of being written.
+// kWordsMax: the occupancy words of the largest segment this instance takes
+// (segments of up to 2^14 cells: one word per thread, the smaller LDS
+// footprint; above: several per thread).
+template <int kWordsMax>
 __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
 {
-    constexpr int kWordsMax = (1 << kSegLog2Max) >> 5;
-    static_assert(kWordsMax <= kSegBlock, "one occupancy word per thread");
+    constexpr int kWordsPerThread = (kWordsMax + kSegBlock - 1) / kSegBlock;
+    static_assert(kWordsMax % kSegBlock == 0 || kWordsMax < kSegBlock, "whole words per thread");
     __shared__ int cnt[kCntCap];                     // per occupied cell of a window: count, start, cursor
     __shared__ unsigned bits[kWordsMax];             // occupancy of the segment's cells
     __shared__ int wbase[kWordsMax];                 // occupied cells before each word
@@ -449,15 +453,27 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     }
     __syncthreads();
 
-    // 2. rank bases, occupancy words out
+    // 2. rank bases, occupancy words out: thread t owns the wpt consecutive
+    //    words t wpt .. t wpt + wpt - 1 (one word up to 2^14 cells)
     {
-        const unsigned b = tid < words ? bits[tid] : 0u;
-        int n_occ;
-        const int run = block_excl_scan<kSegBlock>(__popc(b), lds, &n_occ);
-        if (tid < words) {
-            wbase[tid] = run;
-            p.occ[(cell0 >> 5) + tid] = make_uint2(b, (unsigned)(a + run));
+        const int wpt = words > kSegBlock ? words / kSegBlock : 1;
+        const int w0 = tid * wpt;
+        unsigned b[kWordsPerThread];
+        int sum = 0;
+#pragma unroll
+        for (int q = 0; q < kWordsPerThread; ++q) {
+            b[q] = (q < wpt && w0 + q < words) ? bits[w0 + q] : 0u;
+            sum += __popc(b[q]);
         }
+        int n_occ;
+        int run = block_excl_scan<kSegBlock>(sum, lds, &n_occ);
+#pragma unroll
+        for (int q = 0; q < kWordsPerThread; ++q)
+            if (q < wpt && w0 + q < words) {
+                wbase[w0 + q] = run;
+                p.occ[(cell0 >> 5) + w0 + q] = make_uint2(b[q], (unsigned)(a + run));
+                run += __popc(b[q]);
+            }
         if (tid == 0) {
             occ_total = n_occ;
             if (n_occ < P) p.cstart[a + n_occ] = e;
@@ -947,7 +963,10 @@ hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t)
     if (p.n > 0)
         FOF_TIMED(K_SEG_SCATTER, hipLaunchKernelGGL(k_seg_scatter, dim3(seg_tiles), dim3(kBlock), 0, stream, p));
     const dim3 grid((unsigned)p.n_segments), block(kSegBlock);
-    FOF_TIMED(K_CELL_SORT, hipLaunchKernelGGL(k_cell_sort, grid, block, 0, stream, p));
+    if (p.seg_shift <= 14)
+        FOF_TIMED(K_CELL_SORT, hipLaunchKernelGGL(k_cell_sort<(1 << 14) / 32>, grid, block, 0, stream, p));
+    else
+        FOF_TIMED(K_CELL_SORT, hipLaunchKernelGGL(k_cell_sort<(1 << kSegLog2Max) / 32>, grid, block, 0, stream, p));
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ AXES = {
                        (1024, 1024, True), (1024, 2048, False))) + (schedule_bits(giant_skip=True),),
     "link_order": ("index", "random"),
     "compression": ("halving", "depth2"),
-    "segment_log2": (0, 12, 13),
+    "segment_log2": (0, 13, 14, 16),
 }
 DEFAULTS = {"schedule": 0, "link_order": "index", "compression": "halving", "segment_log2": 0}
 DEFAULT_CACHE = os.environ.get("FOF_TUNE_CACHE",

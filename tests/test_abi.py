@@ -40,7 +40,7 @@ def _ctx(**kw):
 
 
 def test_create_rejects_bad_options():
-    for kw in (dict(cell_factor=0.5), dict(cell_factor=float("inf")), dict(segment_log2=5), dict(segment_log2=15),
+    for kw in (dict(cell_factor=0.5), dict(cell_factor=float("inf")), dict(segment_log2=5), dict(segment_log2=17),
                dict(segment_log2=-1), dict(domains=-1), dict(domains=4097)):
         with pytest.raises(fof.FoFError) as e:
             _ctx(**kw)

@@ -178,9 +178,10 @@ def test_kernel_paths_on_hand_cases(dense_min):
 
 
 # The cell sort counts 2^k cells per work-group: small k gives many segments
-# per bucket, k = 14 one segment per bucket; 16^3 and 32^3 cells fill their
-# last segment exactly (the end marker comes from the last work-group).
-@pytest.mark.parametrize("segment_log2", [6, 7, 9, 11, 12, 13, 14])
+# per bucket, k >= 14 one segment per bucket and above 2^14 cells several
+# occupancy words per thread; 16^3 and 32^3 cells fill their last segment
+# exactly (the end marker comes from the last work-group).
+@pytest.mark.parametrize("segment_log2", [6, 7, 9, 11, 12, 13, 14, 15, 16])
 def test_cell_sort_segments(segment_log2):
     n = 120000
     pos = synth.clustered(n, 23, 0, 0.7)
