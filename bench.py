@@ -202,6 +202,9 @@ def parse():
                          "FETCH_SIZE and WRITE_SIZE runs of the same command, with --copy-calibration), add "
                          "the workload's entry to profiles/traffic.json and print a markdown summary")
     ap.add_argument("--counter-workload", default="batched256", help="the workload the counters were taken on")
+    ap.add_argument("--summarize-sq", metavar="DIR", nargs="+", default=None,
+                    help="no GPU work: per-kernel table of the SQ counters in the rocprofv3 counter CSVs under "
+                         "the given directories (instructions per wave, VALU busy share, wait share)")
     return ap.parse_args()
 
 
@@ -211,6 +214,41 @@ FOF_KEYS = ("cell_factor", "dense_min", "schedule", "link_order", "compression",
 
 def fof_kwargs(cfg: dict) -> dict:
     return {k: cfg[k] for k in FOF_KEYS if k in cfg}
+
+
+def summarize_sq(dirs) -> str:
+    """Markdown table of SQ counters per kernel (mean over dispatches) from
+    rocprofv3 --pmc runs: VALU, SALU, LDS and vector-memory instructions per
+    wave, VALU instructions per dispatch, and the share of wave cycles spent
+    waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES)."""
+    import csv
+    import collections
+
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in dirs:
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if "fof::" in r["Kernel_Name"]:
+                vals[_kernel_key(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["| kernel | waves | VALU/wave | SALU/wave | LDS/wave | VMEM rd/wave | VALU total | wait share |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
+
+    def mean(c, k):
+        v = vals[k].get(c)
+        return statistics.mean(v) if v else None
+
+    for k in sorted(vals, key=lambda k: -(mean("SQ_WAVE_CYCLES", k) or 0)):
+        waves = mean("SQ_WAVES", k)
+        if not waves:
+            continue
+        cell = []
+        for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD"):
+            m = mean(c, k)
+            cell.append("-" if m is None else f"{m / waves:.0f}")
+        wa, wc = mean("SQ_WAIT_ANY", k), mean("SQ_WAVE_CYCLES", k)
+        wait = "-" if wa is None or not wc else f"{wa / wc:.2f}"
+        tv = mean("SQ_INSTS_VALU", k)
+        lines.append(f"| `{k}` | {waves:.0f} | " + " | ".join(cell) + f" | {0 if tv is None else tv:.3g} | {wait} |")
+    return "\n".join(lines) + "\n"
 
 
 def choose(tune, pos, w, predicate, args, **kw):
@@ -555,7 +593,10 @@ def side_large(args, torch, fof, tune, synth, dev, name, both, steps):
     line = {"n_particles": n}
     res = {}
     for predicate in (("fp32_filter", "fp64") if both else ("fp32_filter",)):
-        cfg = choose(tune, pos, w, predicate, args, cell_factors=(0.0, 2.0), dense_mins=(16, 32), axes={})
+        # a reduced search at this size: two cell sizes, two thresholds, and
+        # whether to skip the giant group
+        cfg = choose(tune, pos, w, predicate, args, cell_factors=(0.0, 2.0), dense_mins=(16, 32),
+                     axes={"schedule": (0, fof.schedule_bits(giant_skip=True))})
         log(f"{name}: {predicate} {cfg}")
         f = fof.FoF(predicate, **fof_kwargs(cfg))
         label, size = f.outputs(n)
@@ -582,6 +623,9 @@ def main():
     args = parse()
     if args.ingest_counters:
         print(ingest_counters(args.ingest_counters, args.counter_workload), end="")
+        return
+    if args.summarize_sq:
+        print(summarize_sq(args.summarize_sq), end="")
         return
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on exactly one GPU (asked for --gpus {args.gpus}); "

@@ -220,7 +220,7 @@ void fp32_thresholds(BoxDev &b, double lx)
 }
 
 constexpr int kDefaultDenseMin = 32;
-constexpr int kMaxSubK = 10;             // at most 1000 sub-cells per dense cell
+constexpr int kMaxSubK = 8;              // at most 512 sub-cells per dense cell
 constexpr int kDenseBlocks = 2048;
 constexpr int kSparseBlocks = 1024;
 

@@ -131,7 +131,7 @@ int64_t max_dense_items(int64_t n, int dense_min);
 // Kernels in launch order; the ids index per-kernel timings.
 enum KernelId {
     K_CLEAR, K_BUCKET_HIST, K_BUCKET_SCAN, K_BUCKET_SCATTER, K_SEG_HIST, K_SEG_SCAN, K_SEG_SCATTER, K_CELL_SORT,
-    K_LINK_SPARSE, K_UNION_EDGES, K_LINK_DENSE, K_FLATTEN, K_RESOLVE, K_GATHER, K_COUNT_KERNELS
+    K_LINK_SPARSE, K_UNION_EDGES, K_PREMERGE, K_LINK_DENSE, K_FLATTEN, K_RESOLVE, K_GATHER, K_COUNT_KERNELS
 };
 const char *kernel_name(int k);
 

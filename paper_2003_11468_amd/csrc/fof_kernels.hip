@@ -922,7 +922,7 @@ const char *kernel_name(int k)
     static const char *names[K_COUNT_KERNELS] = {
         "k_clear", "k_bucket_hist", "k_bucket_scan", "k_bucket_scatter", "k_seg_hist", "k_seg_scan", "k_seg_scatter",
         "k_cell_sort",
-        "k_link_sparse", "k_union_edges", "k_link_dense", "k_flatten", "k_resolve", "k_gather"};
+        "k_link_sparse", "k_union_edges", "k_dense_premerge", "k_link_dense", "k_flatten", "k_resolve", "k_gather"};
     return (k >= 0 && k < K_COUNT_KERNELS) ? names[k] : "?";
 }
 

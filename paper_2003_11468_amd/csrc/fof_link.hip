@@ -969,16 +969,19 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
 
 // Pre-merge of dense cells (before the pair search): one wavefront per dense
 // cell splits it into k^3 sub-cells small enough that any two particles of
-// one sub-cell are linked, and hooks every particle under the lowest
-// particle of its sub-cell. When the sub-cells are smaller still (sub_adj:
+// one sub-cell are linked. When the sub-cells are smaller still (sub_adj:
 // any two particles of two sub-cells that touch, across a face, an edge or a
-// corner, are linked), a union-find over the occupied sub-cells in LDS first
-// joins every two touching occupied sub-cells, and each particle is hooked
-// under a particle of its joined set. Only linked pairs (directly or through
-// a chain) are merged, so the groups found are unchanged; the pair search
-// then meets few groups per dense cell, and its staging drops the candidates
-// of the home particles' own group.
-constexpr int kMaxSub = 1000;
+// corner, are linked), a union-find over the occupied sub-cells in LDS joins
+// every two touching occupied sub-cells. Every particle is then hooked
+// straight under the particle of highest hooking priority (smallest key) of
+// its sub-cell or joined set: only particles joined by chains of linked pairs
+// are merged, so the groups are unchanged, and the pair search meets few
+// groups per dense cell (its staging drops the candidates of the home
+// particles' own group). The particles of dense cells are still their own
+// roots when this runs (the per-particle search and its union pass never
+// link them) and each dense cell has one wavefront, so the hooks are plain
+// stores.
+constexpr int kMaxSub = 512;
 
 __device__ __forceinline__ int lds_ld(int *a) { return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 __device__ __forceinline__ void lds_st(int *a, int v)
@@ -1018,12 +1021,16 @@ __device__ __forceinline__ void lds_unite(int *f, int a, int b)
 
 __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
 {
-    __shared__ int rep[kWaves][kMaxSub];    // lowest particle of each sub-cell (INT_MAX: empty)
+    // per sub-cell: (hooking key << 32 | particle) of its first particle, ~0 when empty
+    __shared__ unsigned long long rep[kWaves][kMaxSub];
     __shared__ int join[kWaves][kMaxSub];   // forest over the sub-cells (sub_adj)
+    __shared__ int used[kWaves][kMaxSub];   // the occupied sub-cells (sub_adj)
     const int wid = threadIdx.x >> 6, lane = lane_id();
-    int *rp = rep[wid];
+    unsigned long long *rp = rep[wid];
     int *jf = join[wid];
-    unsigned retries = 0;
+    int *ul = used[wid];
+    const bool rnd = p.link_random != 0;
+    constexpr unsigned long long kEmpty = ~0ull;
     const int n_items = (int)p.counters->n_items;
     const XcdRange xr = xcd_range(n_items, kWaves, wid);
     for (int64_t it = xr.first; it < xr.end; it += xr.stride) {
@@ -1043,7 +1050,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
         const int cx = local % nc, cy = (local / nc) % nc, cz = local / (nc * nc);
         const int nsub = k * k * k;
         for (int t = lane; t < nsub; t += 64) {
-            rp[t] = INT_MAX;
+            rp[t] = kEmpty;
             jf[t] = t;
         }
         __builtin_amdgcn_wave_barrier();
@@ -1056,33 +1063,48 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
             const int sz = min(max((int)floor(fz * k), 0), k - 1);
             return (sz * k + sy) * k + sx;
         };
-        for (int j = cs + lane; j < ce; j += 64) atomicMin(&rp[sub_of(j)], j);
+        for (int j = cs + lane; j < ce; j += 64)
+            atomicMin(&rp[sub_of(j)], ((unsigned long long)link_key(j, rnd) << 32) | (unsigned)j);
         __builtin_amdgcn_wave_barrier();
         if (adj) {
-            // join touching occupied sub-cells: each one with the 13 of its
-            // 26 neighbours that come after it
-            for (int t = lane; t < nsub; t += 64) {
-                if (rp[t] == INT_MAX) continue;
+            // the occupied sub-cells, listed (there are at most as many as
+            // particles), then each joined with the touching occupied ones
+            // among the 13 of its 26 neighbours that come after it
+            int n_used = 0;
+            for (int t0 = 0; t0 < nsub; t0 += 64) {
+                const int t = t0 + lane;
+                const bool occ = t < nsub && rp[t] != kEmpty;
+                const unsigned long long m = __ballot(occ);
+                if (occ) ul[n_used + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = t;
+                n_used += __popcll(m);
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int q = lane; q < n_used; q += 64) {
+                const int t = ul[q];
                 const int sx = t % k, sy = (t / k) % k, sz = t / (k * k);
                 for (int o = 14; o < 27; ++o) {
                     const int ux = sx + o % 3 - 1, uy = sy + (o / 3) % 3 - 1, uz = sz + o / 9 - 1;
                     if (ux < 0 || ux >= k || uy < 0 || uy >= k || uz >= k) continue;
                     const int u = (uz * k + uy) * k + ux;
-                    if (rp[u] != INT_MAX) lds_unite(jf, t, u);
+                    if (rp[u] != kEmpty) lds_unite(jf, t, u);
                 }
+            }
+            __builtin_amdgcn_wave_barrier();
+            // the particle of smallest key of each joined set, at its root sub-cell
+            for (int q = lane; q < n_used; q += 64) {
+                const int t = ul[q];
+                const int r = lds_find(jf, t);
+                if (r != t) atomicMin(&rp[r], rp[t]);
             }
             __builtin_amdgcn_wave_barrier();
         }
         for (int j = cs + lane; j < ce; j += 64) {
             const int sj = sub_of(j);
-            const int r = rp[adj ? lds_find(jf, sj) : sj];
-            if (r != j) retries += unite(p.parent, j, r, p.link_random, p.find_mode);
+            const int r = (int)(unsigned)(rp[adj ? lds_find(jf, sj) : sj] & 0xffffffffull);
+            if (r != j) p.parent[j] = r;   // a key smaller than j's: a valid hook of a root
         }
         __builtin_amdgcn_wave_barrier();
-    }
-    if (p.stats) {
-        const unsigned long long r = wave_sum_u64((unsigned long long)retries);
-        if (lane == 0 && r) atomicAdd(&p.counters->cas_retries, r);
     }
 }
 
@@ -1348,10 +1370,13 @@ void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
     if (t) t->mark(K_UNION_EDGES, false, stream);
     hipLaunchKernelGGL((k_union_edges<kStats>), dim3(kUnionParts * kEdgeSlices), dim3(kBlock), 0, stream, p);
     if (t) t->mark(K_UNION_EDGES, true, stream);
-    if (t) t->mark(K_LINK_DENSE, false, stream);
     // the sub-cell pre-merge would merge across slab faces: not in domain mode
-    if (p.domains <= 1 && p.premerge)
+    if (p.domains <= 1 && p.premerge) {
+        if (t) t->mark(K_PREMERGE, false, stream);
         hipLaunchKernelGGL(k_dense_premerge, dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
+        if (t) t->mark(K_PREMERGE, true, stream);
+    }
+    if (t) t->mark(K_LINK_DENSE, false, stream);
     if (p.domains > 1 || p.link_random)
         hipLaunchKernelGGL((k_link_dense<kFP64, kStats, true>), dim3((unsigned)p.dense_blocks), dim3(kBlock), 0,
                            stream, p);

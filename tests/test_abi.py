@@ -202,8 +202,9 @@ def test_kernel_times_need_the_option():
         assert e.value.status == fof.FOF_ERR_BAD_STATE
     finally:
         fof.fof_destroy(ctx)
-    names = [fof.fof_kernel_name(k) for k in range(14)]
-    assert names[0] == "k_clear" and "k_link_dense" in names and "?" not in names
+    names = [fof.fof_kernel_name(k) for k in range(15)]
+    assert names[0] == "k_clear" and "k_link_dense" in names and "k_dense_premerge" in names and "?" not in names
+    assert fof.fof_kernel_name(15) == "?"
     assert fof.fof_kernel_name(99) == "?"
 
 

@@ -104,3 +104,16 @@ def test_exactness_compares_every_output():
     assert bench.same(a, (np.arange(5), np.ones(5), np.array([3])))
     assert not bench.same(a, (np.arange(5), np.ones(5), np.array([4])))        # group counts differ
     assert not bench.same(a, (np.arange(5), np.zeros(5), np.array([3])))       # sizes differ
+
+
+def test_sq_summary_per_wave(tmp_path):
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    k = "void fof::(anonymous namespace)::k_link_dense<false, false, false>(fof::Plan)"
+    _write(str(tmp_path / "a" / "run_counter_collection.csv"), hdr,
+           [[k, "SQ_WAVES", 100], [k, "SQ_INSTS_VALU", 5000], [k, "SQ_WAVE_CYCLES", 1000], [k, "SQ_WAVES", 100],
+            [k, "SQ_INSTS_VALU", 7000], [k, "SQ_WAVE_CYCLES", 1000]])
+    _write(str(tmp_path / "b" / "run_counter_collection.csv"), hdr, [[k, "SQ_WAIT_ANY", 700]])
+    t = bench.summarize_sq([str(tmp_path / "a"), str(tmp_path / "b")])
+    row = [l for l in t.splitlines() if "k_link_dense" in l][0]
+    cells = [c.strip() for c in row.split("|")]
+    assert cells[2] == "100" and cells[3] == "60" and cells[-2] == "0.70"

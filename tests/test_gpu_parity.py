@@ -614,7 +614,7 @@ def test_kernel_times_cover_every_kernel():
         for _ in range(3):
             f.run(pos, [0, n], 1.0, synth.linking_length(0.2, n))
         kt = f.kernel_times()
-        assert set(kt) == {fof.fof_kernel_name(k) for k in range(14)}
+        assert set(kt) == {fof.fof_kernel_name(k) for k in range(15)}
         for name, (ms, launches) in kt.items():
             assert launches == 3 and ms > 0.0, name
         assert all(c == 0 for _, c in f.kernel_times().values())   # the record was cleared

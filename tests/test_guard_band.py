@@ -142,14 +142,14 @@ def test_premerge_sub_cells_are_inside_the_linking_length():
         need_one = side * np.sqrt(3.0) / (lx * (1 - 1e-6))
         need_adj = 2.0 * need_one
         if k:
-            assert 1 <= k <= 10
+            assert 1 <= k <= 8
             s = side / k
             if adj:
                 assert k == int(np.ceil(need_adj))
                 assert 2.0 * s * np.sqrt(3.0) <= lx * (1 - 1e-6) * (1 + 1e-12)
                 reach = 2.0 * s        # far corners of two sub-cells touching at a corner
             else:
-                assert need_adj > 10 and k == int(np.ceil(need_one))
+                assert need_adj > 8 and k == int(np.ceil(need_one))
                 assert s * np.sqrt(3.0) <= lx * (1 - 1e-6) * (1 + 1e-12)
                 reach = s              # far corners of one sub-cell
             # the FP64 predicate of two such points links
@@ -158,6 +158,6 @@ def test_premerge_sub_cells_are_inside_the_linking_length():
             t = b.astype(np.float64) - a.astype(np.float64)
             assert float((t[0] * t[0] + t[1] * t[1]) + t[2] * t[2]) < info["l2"]
         else:
-            assert need_one > 10 and adj == 0
+            assert need_one > 8 and adj == 0
         seen.add((k, adj))
     assert (0, 0) in seen and any(a for _, a in seen) and any(k and not a for k, a in seen)
