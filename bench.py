@@ -593,9 +593,9 @@ def side_large(args, torch, fof, tune, synth, dev, name, both, steps):
     line = {"n_particles": n}
     res = {}
     for predicate in (("fp32_filter", "fp64") if both else ("fp32_filter",)):
-        # a reduced search at this size: two cell sizes, two thresholds, and
+        # a reduced search at this size: three cell sizes, two thresholds, and
         # whether to skip the giant group
-        cfg = choose(tune, pos, w, predicate, args, cell_factors=(0.0, 2.0), dense_mins=(16, 32),
+        cfg = choose(tune, pos, w, predicate, args, cell_factors=(0.0, 1.5, 2.0), dense_mins=(16, 32),
                      axes={"schedule": (0, fof.schedule_bits(giant_skip=True))})
         log(f"{name}: {predicate} {cfg}")
         f = fof.FoF(predicate, **fof_kwargs(cfg))

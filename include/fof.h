@@ -202,7 +202,8 @@ fof_status fof_set_stream(fof_ctx *ctx, void *hip_stream);
  * h_box_offsets has n_boxes + 1 non-decreasing entries starting at 0; the
  * total count must be below 2^31. Each box needs L > 0 finite, 0 < l_x and at
  * least 3 cells of side >= l_x (1 + 2^-20) per axis (so l_x < L / 3).
- * Errors: FOF_ERR_INVALID_ARG, FOF_ERR_UNSUPPORTED (more than 2^31 - 2 cells). */
+ * Errors: FOF_ERR_INVALID_ARG, FOF_ERR_UNSUPPORTED (a box of more than 2048
+ * cells per axis, or more than 2^34 cells over all boxes). */
 fof_status fof_workspace_bytes(fof_ctx *ctx, const int64_t *h_box_offsets, const double *h_box,
                                const double *h_lx, int32_t n_boxes, size_t *bytes);
 

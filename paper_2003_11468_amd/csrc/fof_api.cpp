@@ -19,7 +19,10 @@ using fof::Counters;
 using fof::Plan;
 
 constexpr size_t kAlign = 256;
-constexpr int64_t kMaxCells = (int64_t)INT32_MAX - 2;
+// Cells over all boxes: 256 buckets of at most 2^kMaxSubLog2 segments of at
+// most 2^kSegLog2Max cells.
+constexpr int64_t kMaxCells = (int64_t)1 << (8 + fof::kMaxSubLog2 + fof::kSegLog2Max);
+constexpr double kMaxCellsPerAxis = 2048.0;   // a box of 2048^3 cells is 2^33
 constexpr int kMaxDomains = 4096;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -186,7 +189,7 @@ fof_status cells_per_axis(const fof_options &o, int64_t n_box, double L, double 
     else want = std::floor(std::cbrt((double)(n_box > 1 ? n_box : 1)) + 1e-9);
     double nc = want < fit ? want : fit;
     if (nc < 3.0) nc = 3.0;
-    if (nc > 1290.0) return FOF_ERR_UNSUPPORTED;   // nc^3 must stay below 2^31
+    if (nc > kMaxCellsPerAxis) return FOF_ERR_UNSUPPORTED;
     *nc_out = (int64_t)nc;
     return FOF_OK;
 }
@@ -296,6 +299,7 @@ fof_status make_layout(const fof_options &o, int64_t n_total, int64_t cells, int
         while (p.seg_shift < fof::kSegLog2Auto && (double)(int64_t(1) << (p.seg_shift + 1)) <= want) ++p.seg_shift;
     }
     if (p.seg_shift < p.bucket_shift - fof::kMaxSubLog2) p.seg_shift = p.bucket_shift - fof::kMaxSubLog2;
+    if (p.seg_shift > fof::kSegLog2Max) return FOF_ERR_UNSUPPORTED;   // more cells than the levels hold
     if (p.bucket_shift < p.seg_shift) p.bucket_shift = p.seg_shift;
     p.sub_log2 = p.bucket_shift - p.seg_shift;
     p.n_buckets = (int32_t)((last >> p.bucket_shift) + 1);

@@ -221,12 +221,13 @@ __device__ __forceinline__ unsigned unite(int *parent, int a, int b, bool random
 // Sorted slots [x, y) of cell c: its occupancy word gives the rank of the cell
 // among the occupied cells, and cstart the slot of that rank (an empty cell
 // gives an empty range).
-__device__ __forceinline__ int2 cell_span(const Plan &p, int c)
+__device__ __forceinline__ int2 cell_span(const Plan &p, int64_t c)
 {
     const uint2 w = p.occ[c >> 5];
-    const int r = (int)w.y + __popc(w.x & ((1u << (c & 31)) - 1u));
+    const unsigned bit = (unsigned)c & 31u;
+    const int r = (int)w.y + __popc(w.x & ((1u << bit) - 1u));
     const int s = p.cstart[r];
-    return make_int2(s, ((w.x >> (c & 31)) & 1u) ? p.cstart[r + 1] : s);
+    return make_int2(s, ((w.x >> bit) & 1u) ? p.cstart[r + 1] : s);
 }
 
 // ------------------------------------------------------------ wave utils --
@@ -337,13 +338,13 @@ __device__ __forceinline__ void wave_min_by_key(int2 *arr, int key, int v)
     }
 }
 
-__device__ __forceinline__ int particle_cell(const BoxDev &bd, float x, float y, float z)
+__device__ __forceinline__ int64_t particle_cell(const BoxDev &bd, float x, float y, float z)
 {
     const int nc = bd.nc;
     int cx = cell_coord(x, bd.inv_h, nc);
     int cy = cell_coord(y, bd.inv_h, nc);
     int cz = cell_coord(z, bd.inv_h, nc);
-    return (int)(bd.cell_base + ((int64_t)cz * nc + cy) * nc + cx);
+    return bd.cell_base + ((int64_t)cz * nc + cy) * nc + cx;
 }
 
 // Work-groups are dispatched round-robin over the 8 XCDs, each with its own

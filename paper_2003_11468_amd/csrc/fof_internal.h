@@ -101,7 +101,7 @@ struct Plan {
     int32_t *gmin;          // [n] smallest original index of the group, at its root
     int32_t *parent;        // [n] union-find forest over sorted indices
     int32_t *gsize;         // [n] group member count at roots (sorted indices)
-    int4 *items;            // [max_items] dense work: {cell, first home particle, box, 0}
+    int4 *items;            // [max_items] dense work: {cx | cy << 16, first home particle, box, cz}
     int2 *edges;            // [max_edges] linked pairs found by the sparse search
     int2 *bnd;              // domain mode: [max_edges] linked pairs across domains, then their root pairs
     unsigned int *edge_fill;   // [kEdgeSlices] pairs appended to each slice (may exceed its capacity)

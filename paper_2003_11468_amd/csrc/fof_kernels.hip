@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(kBlock) k_clear(Plan p)
 
 // Cell key of input particle i; `ok` tells whether its coordinates are finite
 // and inside [0, L).
-__device__ __forceinline__ int input_key(const Plan &p, int64_t i, float &x, float &y, float &z, bool &ok)
+__device__ __forceinline__ int64_t input_key(const Plan &p, int64_t i, float &x, float &y, float &z, bool &ok)
 {
     const int b = p.n_boxes == 1 ? 0 : find_box_wave(p.box_p0, p.n_boxes, i);
     const BoxDev &bd = box_of(p, b);
@@ -105,9 +105,9 @@ __global__ void __launch_bounds__(kBlock) k_bucket_hist(Plan p)
         if (i < p.n) {
             float x, y, z;
             bool ok;
-            const int key = input_key(p, i, x, y, z, ok);
+            const int64_t key = input_key(p, i, x, y, z, ok);
             bad |= !ok;
-            atomicAdd(&cnt[key >> p.bucket_shift], 1);
+            atomicAdd(&cnt[(int)(key >> p.bucket_shift)], 1);
         }
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&p.counters->error, 1u);
@@ -139,8 +139,8 @@ __global__ void __launch_bounds__(kBlock) k_bucket_scatter(Plan p)
         if (i < p.n) {
             float x, y, z;
             bool ok;
-            const int key = input_key(p, i, x, y, z, ok);
-            bk[k] = key >> p.bucket_shift;
+            const int64_t key = input_key(p, i, x, y, z, ok);
+            bk[k] = (int)(key >> p.bucket_shift);
             rk[k] = atomicAdd(&cnt[bk[k]], 1);
             v[k] = make_float4(x, y, z, __int_as_float((int)i));
         }
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(ScanArgs a)
 // ---------------------------------------------------------- segment pass --
 
 // Cell of a staged particle (x, y, z, original index as bits).
-__device__ __forceinline__ int staged_cell(const Plan &p, const float4 &v)
+__device__ __forceinline__ int64_t staged_cell(const Plan &p, const float4 &v)
 {
     const int b = p.n_boxes == 1 ? 0 : find_box_wave(p.box_p0, p.n_boxes, __float_as_int(v.w));
     return particle_cell(box_of(p, b), v.x, v.y, v.z);
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_hist(Plan p)
     for (int s = threadIdx.x; s < subs; s += kBlock) cnt[s] = 0;
     __syncthreads();
     for (int k = lo + (int)threadIdx.x; k < hi; k += kBlock)
-        atomicAdd(&cnt[(staged_cell(p, p.staging[k]) >> p.seg_shift) - seg0], 1);
+        atomicAdd(&cnt[(int)(staged_cell(p, p.staging[k]) >> p.seg_shift) - seg0], 1);
     __syncthreads();
     for (int s = threadIdx.x; s < subs; s += kBlock)
         if (cnt[s]) atomicAdd(p.seg_end + seg0 + s, cnt[s]);
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_scatter(Plan p)
         sb[q] = -1;
         if (k < hi) {
             v[q] = p.staging[k];
-            sb[q] = (staged_cell(p, v[q]) >> p.seg_shift) - seg0;
+            sb[q] = (int)(staged_cell(p, v[q]) >> p.seg_shift) - seg0;
             rk[q] = atomicAdd(&cnt[sb[q]], 1);
         }
     }
@@ -391,8 +391,8 @@ static_assert(kCntCap >= kOrderCap, "a segment placed through LDS is one window"
 // occupied cells than that):
 //  3. particle count per occupied cell, indexed by rank;
 //  4. exclusive prefix over the occupied cells (thread t owns a run);
-//  5. cell starts out, and dense link work items {cell, first home particle,
-//     box, 0}, one per 64 particles of every cell with at least dense_min
+//  5. cell starts out, and dense link work items {cx | cy << 16, first home
+//     particle, box, cz}, one per 64 particles of every cell with at least dense_min
 //     particles (the cell of a rank is found from the rank bases);
 //  6. place the particles: the LDS cursors give each its slot; up to
 //     kOrderCap particles the slot order is kept in LDS and the outputs are
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     __shared__ int occ_total;
     const int j = (int)blockIdx.x;
     const int words = 1 << (p.seg_shift - 5);
-    const int cell0 = j << p.seg_shift;
+    const int64_t cell0 = (int64_t)j << p.seg_shift;
     const int a = j ? p.seg_end[j - 1] : 0;
     const int e = p.seg_end[j];
     const int P = e - a;
@@ -427,12 +427,12 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
     // the segment's cell of a staged particle; a cell outside the segment
     // cannot happen with a consistent partition and is latched, not used
     auto local_cell = [&](const float4 &v) {
-        const int c = staged_cell(p, v) - cell0;
-        if ((unsigned)c >= (unsigned)seg_cells) {
+        const int64_t c = staged_cell(p, v) - cell0;
+        if ((uint64_t)c >= (uint64_t)seg_cells) {
             bad = true;
             return 0;
         }
-        return c;
+        return (int)c;
     };
     for (int w = tid; w < words; w += kSegBlock) bits[w] = 0u;
     __syncthreads();
@@ -554,10 +554,13 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
                         }
                         unsigned m = bits[lo];
                         for (int t = rk - wbase[lo]; t > 0; --t) m &= m - 1u;   // drop the lower occupied cells
-                        const int gc = cell0 + (lo << 5) + (__ffs(m) - 1);
+                        const int64_t gc = cell0 + (lo << 5) + (__ffs(m) - 1);
                         const int bx = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, start);
+                        // the cell's coordinates in its box (nc <= 2^16 per axis)
+                        const int64_t nc = box_of(p, bx).nc, local = gc - box_of(p, bx).cell_base;
+                        const int cx = (int)(local % nc), cy = (int)((local / nc) % nc), cz = (int)(local / (nc * nc));
                         for (int q = 0; q < v; q += 64, ++slot)
-                            if (slot < p.max_items) p.items[slot] = make_int4(gc, start + q, bx, 0);
+                            if (slot < p.max_items) p.items[slot] = make_int4(cx | (cy << 16), start + q, bx, cz);
                     }
                 }
             }

@@ -120,31 +120,27 @@ __device__ __forceinline__ double axis_shift(int code, double L) { return code =
 
 constexpr int kMaxRanges = 10;
 
-struct Ranges {
-    int j0[kMaxRanges], j1[kMaxRanges], code[kMaxRanges];
-    int n = 0;
-    __device__ __forceinline__ void add(int a, int b, int c)
-    {
-        if (b <= a) return;
-#pragma unroll
-        for (int r = 0; r < kMaxRanges; ++r)
-            if (r == n) {
-                j0[r] = a;
-                j1[r] = b;
-                code[r] = c;
-            }
-        ++n;
-    }
+// One candidate range of a home particle: slots [j0, j1) (empty when
+// j1 <= j0) and their periodic shift code.
+struct Span {
+    int j0 = 0, j1 = 0, code = 0;
 };
 
 // The three cells (x = cx-1, cx, cx+1) of one neighbour row, given their
-// boundaries b0..b3 (b_e = start of cell e, b_{e+1} its end when the cells
-// are contiguous) and whether the row wraps at either end. Runs of sparse,
-// memory-contiguous cells are merged into one range: at most two per row.
-__device__ __forceinline__ void add_row(Ranges &R, const int st[3], const int en[3], const int xcode[3],
-                                        int yz_code, int dense_min)
+// boundaries (st[e], en[e]) and whether the row wraps at either end. Runs of
+// sparse, memory-contiguous cells are merged into one range: at most two per
+// row (the cells of a row follow each other in memory except across the
+// wrap, which is at one end, and around a dense middle cell).
+__device__ __forceinline__ void row_spans(const int st[3], const int en[3], const int xcode[3], int yz_code,
+                                          int dense_min, Span &A, Span &B)
 {
     int a = -1, b = -1, code = 0;
+    bool first = true;
+    auto emit = [&](int j0, int j1, int c) {
+        if (first) A = Span{j0, j1, c};
+        else B = Span{j0, j1, c};
+        first = false;
+    };
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const bool sparse = en[e] - st[e] < dense_min;
@@ -153,14 +149,14 @@ __device__ __forceinline__ void add_row(Ranges &R, const int st[3], const int en
             if (a >= 0 && st[e] == b && c == code) {
                 b = en[e];
             } else {
-                if (a >= 0) R.add(a, b, code);
+                if (a >= 0) emit(a, b, code);
                 a = st[e];
                 b = en[e];
                 code = c;
             }
         }
     }
-    if (a >= 0) R.add(a, b, code);
+    if (a >= 0) emit(a, b, code);
 }
 
 // Linked pairs of the sparse search are not merged where they are found: a
@@ -341,7 +337,7 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
     const XcdRange xr = xcd_range(n_tiles, kWaves, wid);
     for (int64_t tile = xr.first; tile < xr.end; tile += xr.stride) {
         const int64_t s64 = tile * 64 + lane;
-        Ranges R;
+        Span R[kMaxRanges];   // own cell, next cell, then two per neighbour row
         float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
         int b = 0;
         if (s64 < p.n) {
@@ -353,12 +349,11 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
             const int cx = cell_coord(pi.x, bd.inv_h, nc);
             const int cy = cell_coord(pi.y, bd.inv_h, nc);
             const int cz = cell_coord(pi.z, bd.inv_h, nc);
-            const int cb = (int)bd.cell_base;
-            const int c = cb + (cz * nc + cy) * nc + cx;
+            const int64_t c = bd.cell_base + ((int64_t)cz * nc + cy) * nc + cx;
             const int *cst = p.cstart;
             const int dense_min = p.dense_min;
             const int seg_shift = p.seg_shift;
-            const int rb0 = c - cx;
+            const int64_t rb0 = c - cx;
             // Boundaries of the own row and the four neighbour rows (dy, dz) =
             // (1, 0), (-1, 1), (0, 1), (1, 1): with the own cell these hold the
             // 13 half-shell cells. Occupancy words (bits and rank base per 32
@@ -367,12 +362,12 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
             const uint2 *occ = p.occ;
             typedef unsigned uint4a8 __attribute__((ext_vector_type(4), aligned(8)));
             typedef int int4a4 __attribute__((ext_vector_type(4), aligned(4)));
-            auto rank_in = [](unsigned bits, unsigned base, int cell_index) {
-                return (int)base + __popc(bits & ((1u << (cell_index & 31)) - 1u));
+            auto rank_in = [](unsigned bits, unsigned base, int64_t cell_index) {
+                return (int)base + __popc(bits & ((1u << ((unsigned)cell_index & 31u)) - 1u));
             };
-            auto span = [&](int cell_index, int &s0, int &s1) {   // left at 0, 0 for an empty cell
+            auto span = [&](int64_t cell_index, int &s0, int &s1) {   // left at 0, 0 for an empty cell
                 const uint2 w = occ[cell_index >> 5];
-                if ((w.x >> (cell_index & 31)) & 1u) {
+                if ((w.x >> ((unsigned)cell_index & 31u)) & 1u) {
                     const int r = rank_in(w.x, w.y, cell_index);
                     s0 = cst[r];
                     s1 = cst[r + 1];
@@ -381,7 +376,8 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
             const int nxp = cx + 1 < nc ? cx + 1 : 0;
             const bool inner = cx >= 1 && cx + 1 < nc;
             const int rdy[4] = {1, -1, 0, 1}, rdz[4] = {0, 1, 1, 1};
-            int rb[4], yz[4], c0[4];
+            int64_t rb[4], c0[4];
+            int yz[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int ny = cy + rdy[r], nz = cz + rdz[r], code = 0;
@@ -389,7 +385,7 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
                 else if (ny < 0) { ny += nc; code |= 1 << 2; }
                 if (nz >= nc) { nz -= nc; code |= 2 << 4; }
                 yz[r] = code;
-                rb[r] = cb + (nz * nc + ny) * nc;
+                rb[r] = bd.cell_base + ((int64_t)nz * nc + ny) * nc;
                 c0[r] = rb[r] + (inner ? cx - 1 : 0);
             }
             // Two rounds of loads, each issued whole before any of its results
@@ -409,15 +405,16 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
             unsigned mr[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                mr[r] = (unsigned)((((uint64_t)wr[r].x | ((uint64_t)wr[r].z << 32)) >> (c0[r] & 31)) & 7u);
+                mr[r] = (unsigned)((((uint64_t)wr[r].x | ((uint64_t)wr[r].z << 32)) >> ((unsigned)c0[r] & 31u)) & 7u);
                 qr[r] = *reinterpret_cast<const int4a4 *>(cst + rank_in(wr[r].x, wr[r].y, c0[r]));
             }
             const int own_start = qo.x, own_end = qo.y;
             int nxt_start = 0, nxt_end = 0;
             if (nxp && ((c ^ (c + 1)) >> seg_shift) == 0) {
                 // the next cell in the same segment: its entries follow the own cell's
-                const unsigned nbits = ((c + 1) & 31) ? wo.x : wo.z;
-                if ((nbits >> ((c + 1) & 31)) & 1u) {
+                const unsigned b1 = (unsigned)(c + 1) & 31u;
+                const unsigned nbits = b1 ? wo.x : wo.z;
+                if ((nbits >> b1) & 1u) {
                     nxt_start = qo.y;
                     nxt_end = qo.z;
                 }
@@ -458,10 +455,10 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
                 // own cell above s, then cell cx + 1 (across the high x face when cx is the top cell)
                 const int xcode_next = cx + 1 < nc ? 0 : 2;
                 if (nxt_end - nxt_start < dense_min && xcode_next == 0 && nxt_start == own_end) {
-                    R.add(s + 1, nxt_end, 0);
+                    R[0] = Span{s + 1, nxt_end, 0};
                 } else {
-                    R.add(s + 1, own_end, 0);
-                    if (nxt_end - nxt_start < dense_min) R.add(nxt_start, nxt_end, xcode_next);
+                    R[0] = Span{s + 1, own_end, 0};
+                    if (nxt_end - nxt_start < dense_min) R[1] = Span{nxt_start, nxt_end, xcode_next};
                 }
                 const int xcode[3] = {cx == 0 ? 1 : 0, 0, cx + 1 == nc ? 2 : 0};
 #pragma unroll
@@ -473,29 +470,32 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
                         for (int e = 0; e < 3; ++e)
                             if (!((r == 0 || r == 2) && e == 1)) en[r][e] = st[r][e];
                     }
-                    add_row(R, st[r], en[r], xcode, yz[r], dense_min);
+                    row_spans(st[r], en[r], xcode, yz[r], dense_min, R[2 + 2 * r], R[3 + 2 * r]);
                 }
             }
         }
         // flatten the units of the wave: unit and pair offsets by prefix sums
-        int my_pairs = 0;
+        int my_pairs = 0, my_units = 0;
 #pragma unroll
         for (int r = 0; r < kMaxRanges; ++r)
-            if (r < R.n) my_pairs += R.j1[r] - R.j0[r];
-        const int unit_incl = wave_incl_scan(R.n);
+            if (R[r].j1 > R[r].j0) {
+                my_pairs += R[r].j1 - R[r].j0;
+                ++my_units;
+            }
+        const int unit_incl = wave_incl_scan(my_units);
         const int pair_incl = wave_incl_scan(my_pairs);
         const int n_units = __shfl(unit_incl, 63, 64);
         const int n_pairs = __shfl(pair_incl, 63, 64);
         if (n_pairs == 0) continue;
         {
-            int u = unit_incl - R.n, pr = pair_incl - my_pairs;
+            int u = unit_incl - my_units, pr = pair_incl - my_pairs;
 #pragma unroll
             for (int r = 0; r < kMaxRanges; ++r)
-                if (r < R.n) {
+                if (R[r].j1 > R[r].j0) {
                     L.start[u] = pr;
-                    L.j0[u] = R.j0[r];
-                    L.tag[u] = R.code[r] | (lane << 8);
-                    pr += R.j1[r] - R.j0[r];
+                    L.j0[u] = R[r].j0;
+                    L.tag[u] = R[r].code | (lane << 8);
+                    pr += R[r].j1 - R[r].j0;
                     ++u;
                 }
             if (lane == 63) L.start[n_units] = n_pairs;
@@ -884,11 +884,13 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
     const XcdRange xr = xcd_range(n_items, kWaves, wid);   // items come in cell order
     for (int64_t it = xr.first; it < xr.end; it += xr.stride) {
         const int4 item = p.items[it];
-        const int c = __builtin_amdgcn_readfirstlane(item.x);
+        const int cxy = __builtin_amdgcn_readfirstlane(item.x);
         const int first = __builtin_amdgcn_readfirstlane(item.y);
         const int b = __builtin_amdgcn_readfirstlane(item.z);
+        const int cx = cxy & 0xffff, cy = cxy >> 16, cz = __builtin_amdgcn_readfirstlane(item.w);
         const BoxDev &bd = box_of(p, b);
-        const int nc = bd.nc, cb = (int)bd.cell_base;
+        const int nc = bd.nc;
+        const int64_t cb = bd.cell_base;
         BoxRegs br;
         br.L = bd.L;
         br.half = bd.half;
@@ -897,8 +899,6 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
         br.hi32 = bd.hi32;
         br.L32 = bd.L32;
         br.strict = p.strict != 0;
-        const int local = c - cb;
-        const int cx = local % nc, cy = (local / nc) % nc, cz = local / (nc * nc);
         // the 27 neighbour cells, one per lane (lanes 0-26, neighbour
         // nb = 9 (dz + 1) + 3 (dy + 1) + dx + 1), looked up at once; code:
         // per axis 1 = the neighbour is the top cell across the low face,
@@ -909,7 +909,7 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
             if (nx < 0) { nx += nc; code |= 1; } else if (nx >= nc) { nx -= nc; code |= 2; }
             if (ny < 0) { ny += nc; code |= 1 << 2; } else if (ny >= nc) { ny -= nc; code |= 2 << 2; }
             if (nz < 0) { nz += nc; code |= 1 << 4; } else if (nz >= nc) { nz -= nc; code |= 2 << 4; }
-            const int2 sp = cell_span(p, cb + (nz * nc + ny) * nc + nx);
+            const int2 sp = cell_span(p, cb + ((int64_t)nz * nc + ny) * nc + nx);
             nb_j0 = sp.x;
             nb_j1 = sp.y;
         }
@@ -1035,19 +1035,19 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
     const XcdRange xr = xcd_range(n_items, kWaves, wid);
     for (int64_t it = xr.first; it < xr.end; it += xr.stride) {
         const int4 item = p.items[it];
-        const int c = __builtin_amdgcn_readfirstlane(item.x);
+        const int cxy = __builtin_amdgcn_readfirstlane(item.x);
         const int first = __builtin_amdgcn_readfirstlane(item.y);
         const int b = __builtin_amdgcn_readfirstlane(item.z);
-        const int2 sp = cell_span(p, c);
+        const int cx = cxy & 0xffff, cy = cxy >> 16, cz = __builtin_amdgcn_readfirstlane(item.w);
+        const BoxDev &bd = box_of(p, b);
+        const int nc = bd.nc;
+        const int2 sp = cell_span(p, bd.cell_base + ((int64_t)cz * nc + cy) * nc + cx);
         const int cs = __builtin_amdgcn_readfirstlane(sp.x);
         if (first != cs) continue;   // the cell's first item does the whole cell
-        const BoxDev &bd = box_of(p, b);
         const int k = bd.sub_k;
         if (k == 0) continue;
         const bool adj = bd.sub_adj != 0;
         const int ce = __builtin_amdgcn_readfirstlane(sp.y);
-        const int nc = bd.nc, local = c - (int)bd.cell_base;
-        const int cx = local % nc, cy = (local / nc) % nc, cz = local / (nc * nc);
         const int nsub = k * k * k;
         for (int t = lane; t < nsub; t += 64) {
             rp[t] = kEmpty;
@@ -1291,7 +1291,8 @@ __global__ void __launch_bounds__(kBlock) k_link_rest(Plan p)
         const int s = active ? (int)s64 : 0;
         const int g = find_root(p.parent, p.counters->giant, p.find_mode, rnd);
         if (active) active = find_root(p.parent, s, p.find_mode, rnd) != g;
-        int b = 0, cx = 0, cy = 0, cz = 0, nc = 3, cb = 0;
+        int b = 0, cx = 0, cy = 0, cz = 0, nc = 3;
+        int64_t cb = 0;
         float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
         BoxPair bx{};
         if (active) {
@@ -1300,11 +1301,11 @@ __global__ void __launch_bounds__(kBlock) k_link_rest(Plan p)
             bx = BoxPair::of(bd);
             h = p.sorted[s];
             nc = bd.nc;
-            cb = (int)bd.cell_base;
+            cb = bd.cell_base;
             cx = cell_coord(h.x, bd.inv_h, nc);
             cy = cell_coord(h.y, bd.inv_h, nc);
             cz = cell_coord(h.z, bd.inv_h, nc);
-            const int2 own = cell_span(p, cb + (cz * nc + cy) * nc + cx);
+            const int2 own = cell_span(p, cb + ((int64_t)cz * nc + cy) * nc + cx);
             if (own.y - own.x >= p.dense_min) active = false;   // the dense search covers its pairs
         }
         if (__ballot(active) == 0) continue;
@@ -1316,7 +1317,7 @@ __global__ void __launch_bounds__(kBlock) k_link_rest(Plan p)
                 if (nx < 0) { nx += nc; code |= 1; } else if (nx >= nc) { nx -= nc; code |= 2; }
                 if (ny < 0) { ny += nc; code |= 1 << 2; } else if (ny >= nc) { ny -= nc; code |= 2 << 2; }
                 if (nz < 0) { nz += nc; code |= 1 << 4; } else if (nz >= nc) { nz -= nc; code |= 2 << 4; }
-                const int2 sp = cell_span(p, cb + (nz * nc + ny) * nc + nx);
+                const int2 sp = cell_span(p, cb + ((int64_t)nz * nc + ny) * nc + nx);
                 if (sp.y - sp.x < p.dense_min) {
                     j0 = sp.x;
                     len = sp.y - sp.x;

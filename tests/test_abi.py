@@ -115,6 +115,24 @@ def test_host_validation(offsets, box, lx):
         fof.fof_destroy(ctx)
 
 
+def test_cells_per_axis_up_to_2048():
+    # up to 2048 cells per axis (2^33 cells in a box), and at most 2^34 cells in all
+    opt = fof.make_options(cell_factor=1.0)
+    assert fof.fof_describe_box(1000, 1.0, 1.0 / 2048.5, opt)["cells_per_axis"] == 2048
+    with pytest.raises(fof.FoFError) as e:
+        fof.fof_describe_box(1000, 1.0, 1.0 / 2049.5, opt)
+    assert e.value.status == fof.FOF_ERR_UNSUPPORTED
+    ctx = _ctx(cell_factor=1.0)
+    try:
+        assert fof.fof_workspace_bytes(ctx, [0, 1000], 1.0, 1.0 / 1800.5) > (1800 ** 3) // 4   # occupancy words
+        assert fof.fof_workspace_bytes(ctx, [0, 10, 20], 1.0, 1.0 / 2048.5) > 0                  # 2^34 cells
+        with pytest.raises(fof.FoFError) as e:
+            fof.fof_workspace_bytes(ctx, [0, 10, 20, 30], 1.0, 1.0 / 2048.5)
+        assert e.value.status == fof.FOF_ERR_UNSUPPORTED
+    finally:
+        fof.fof_destroy(ctx)
+
+
 def test_too_many_cells_is_unsupported():
     ctx = _ctx(cell_factor=1.0)
     try:

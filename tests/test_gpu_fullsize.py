@@ -108,12 +108,12 @@ def _both_predicates_against_oracle(name, cell_factors, dense_mins):
 
 
 def test_clustered512_both_predicates_match_oracle():
-    ref = _both_predicates_against_oracle("clustered512", (0.0, 2.0, 3.0), (16, 32))
+    ref = _both_predicates_against_oracle("clustered512", (0.0, 1.5, 2.0, 3.0), (16, 32))
     assert int(ref[1].max()) >= 2
 
 
 def test_percolate1024_both_predicates_match_oracle():
-    ref = _both_predicates_against_oracle("percolate1024", (0.0, 2.0), (32,))
+    ref = _both_predicates_against_oracle("percolate1024", (0.0, 1.5, 2.0), (32,))
     assert ref[2] < 1024 ** 3
 
 

@@ -145,6 +145,22 @@ def test_cell_sizes(cell_factor):
         assert_single(pos, lx, predicate=predicate, cell_factor=cell_factor)
 
 
+# Above 1290 cells per axis a box has more than 2^31 cells: the cell index is
+# 64-bit in the sort keys, the occupancy words, the neighbour rows and the
+# dense work items. Clustered points so that dense cells and the pre-merge
+# take part too.
+@pytest.mark.parametrize("nc", [1300, 1800])
+def test_more_than_2_to_the_31_cells(nc):
+    n = 150000
+    pos = synth.clustered(n, 23, 0, 0.9, m_max=2e4)
+    lx = 1.0 / (nc + 0.5)
+    assert fof.fof_describe_box(n, 1.0, lx, fof.make_options(cell_factor=1.0))["cells_per_axis"] == nc
+    for predicate in PREDICATES:
+        for dense_min in (8, 1 << 30):
+            ref = assert_single(pos, lx, predicate=predicate, cell_factor=1.0, dense_min=dense_min)
+    assert int(ref[1].max()) >= 8   # groups with many members
+
+
 # dense_min = 1: every non-empty cell is searched by whole wavefronts;
 # dense_min = 1 << 30: every cell per lane; between: both kernels meet.
 @pytest.mark.parametrize("dense_min", [1, 2, 8, 64, 100, 1 << 30])
