@@ -370,8 +370,8 @@ __global__ void __launch_bounds__(kBlock) k_seg_scatter(Plan p)
 constexpr int kSegBlock = 512;
 constexpr int kSegWaves = kSegBlock / 64;
 constexpr int kSegUnroll = 4;            // particles in flight per thread
-constexpr int kOrderCap = 4096;          // segments up to this many particles are placed through LDS
-constexpr int kCntCap = 4096;            // occupied cells counted at once (a window of ranks)
+constexpr int kOrderCap = 4080;          // segments up to this many particles are placed through LDS
+constexpr int kCntCap = 4080;            // occupied cells counted at once (a window of ranks)
 static_assert(kCntCap >= kOrderCap, "a segment placed through LDS is one window");
 
 // One work-group per segment of 2^seg_shift consecutive cells, whose P
@@ -403,7 +403,7 @@ static_assert(kCntCap >= kOrderCap, "a segment placed through LDS is one window"
 // (segments of up to 2^14 cells: one word per thread, the smaller LDS
 // footprint; above: several per thread).
 template <int kWordsMax>
-__global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
+__global__ void __launch_bounds__(kSegBlock) __attribute__((amdgpu_waves_per_eu(kWordsMax <= 1024 ? 8 : 6))) k_cell_sort(Plan p)
 {
     constexpr int kWordsPerThread = (kWordsMax + kSegBlock - 1) / kSegBlock;
     static_assert(kWordsMax % kSegBlock == 0 || kWordsMax < kSegBlock, "whole words per thread");
@@ -500,9 +500,18 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
                 atomicAdd(&cnt[r], 1);
             }
         } else {
-            for (int k = a + tid; k < e; k += kSegBlock) {
-                const int r = rank_of(local_cell(p.staging2[k])) - r0;
-                if ((unsigned)r < (unsigned)nw) atomicAdd(&cnt[r], 1);
+            constexpr int kCountUnroll = 2;
+            for (int k0 = a + tid; k0 < e; k0 += kCountUnroll * kSegBlock) {
+                float4 v[kCountUnroll];
+#pragma unroll
+                for (int q = 0; q < kCountUnroll; ++q)
+                    if (k0 + q * kSegBlock < e) v[q] = p.staging2[k0 + q * kSegBlock];
+#pragma unroll
+                for (int q = 0; q < kCountUnroll; ++q)
+                    if (k0 + q * kSegBlock < e) {
+                        const int r = rank_of(local_cell(v[q])) - r0;
+                        if ((unsigned)r < (unsigned)nw) atomicAdd(&cnt[r], 1);
+                    }
             }
         }
         __syncthreads();
@@ -575,23 +584,35 @@ __global__ void __launch_bounds__(kSegBlock) k_cell_sort(Plan p)
                 else order[local] = (unsigned short)idx;
             }
         } else {
-            for (int k = a + tid; k < e; k += kSegBlock) {
-                const float4 v = p.staging2[k];
-                const int r = rank_of(local_cell(v)) - r0;
-                if ((unsigned)r >= (unsigned)nw) continue;   // another window's particle
-                const int local = atomicAdd(&cnt[r], 1);
-                if ((unsigned)local >= (unsigned)P) {
-                    bad = true;
-                    continue;
+            constexpr int kPlaceUnroll = 2;
+            for (int k0 = a + tid; k0 < e; k0 += kPlaceUnroll * kSegBlock) {
+                float4 v[kPlaceUnroll];
+                int kk[kPlaceUnroll];
+#pragma unroll
+                for (int q = 0; q < kPlaceUnroll; ++q)
+                    if (k0 + q * kSegBlock < e) {
+                        v[q] = p.staging2[k0 + q * kSegBlock];
+                        kk[q] = p.stage2_k[k0 + q * kSegBlock];
+                    }
+#pragma unroll
+                for (int q = 0; q < kPlaceUnroll; ++q) {
+                    if (k0 + q * kSegBlock >= e) continue;
+                    const int r = rank_of(local_cell(v[q])) - r0;
+                    if ((unsigned)r >= (unsigned)nw) continue;   // another window's particle
+                    const int local = atomicAdd(&cnt[r], 1);
+                    if ((unsigned)local >= (unsigned)P) {
+                        bad = true;
+                        continue;
+                    }
+                    const int dst = a + local;
+                    const int i = __float_as_int(v[q].w);
+                    p.sorted[dst] = make_float4(v[q].x, v[q].y, v[q].z, 0.0f);
+                    p.orig[dst] = i;
+                    p.gmin[dst] = i;
+                    p.parent[dst] = dst;
+                    p.gsize[dst] = 1;
+                    p.kmap[dst] = kk[q];
                 }
-                const int dst = a + local;
-                const int i = __float_as_int(v.w);
-                p.sorted[dst] = make_float4(v.x, v.y, v.z, 0.0f);
-                p.orig[dst] = i;
-                p.gmin[dst] = i;
-                p.parent[dst] = dst;
-                p.gsize[dst] = 1;
-                p.kmap[dst] = p.stage2_k[k];
             }
         }
         slot0 += total;
@@ -968,6 +989,8 @@ hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t)
     const dim3 grid((unsigned)p.n_segments), block(kSegBlock);
     if (p.seg_shift <= 14)
         FOF_TIMED(K_CELL_SORT, hipLaunchKernelGGL(k_cell_sort<(1 << 14) / 32>, grid, block, 0, stream, p));
+    else if (p.seg_shift == 15)
+        FOF_TIMED(K_CELL_SORT, hipLaunchKernelGGL(k_cell_sort<(1 << 15) / 32>, grid, block, 0, stream, p));
     else
         FOF_TIMED(K_CELL_SORT, hipLaunchKernelGGL(k_cell_sort<(1 << kSegLog2Max) / 32>, grid, block, 0, stream, p));
     return hipGetLastError();
