@@ -110,7 +110,10 @@ typedef struct {
                                 found from a sample of 4096 roots, then the full periodic shell is
                                 searched, both ways, from the particles outside that group alone (pairs
                                 inside it are never visited). Pays off when one group spans most of the
-                                box; not with domains > 1 */
+                                box; not with domains > 1;
+                                bit 6: the per-particle search does not join the links inside its tiles
+                                of 64 consecutive particles (by default it does, in a bit matrix, and
+                                only the links between tiles go to the union pass) */
     int32_t compression;     /* path compression of the finds (paper, Section 3.4.3): 0 = path halving
                                 (each visited node re-pointed to its grandparent; default); 1 = a path is
                                 compressed onto its root only when it is at least 2 long. Same labels */

@@ -286,12 +286,12 @@ COMPRESSIONS = {"halving": 0, "depth2": 1}   # fof_options.compression
 
 
 def schedule_bits(sparse_grid: int = 1024, dense_grid: int = 2048, premerge: bool = True,
-                  giant_skip: bool = False) -> int:
+                  giant_skip: bool = False, tile_join: bool = True) -> int:
     """fof_options.schedule from its parts (grids of the two persistent link kernels, pre-merge,
-    giant-component skip)."""
+    giant-component skip, links inside a tile joined by the search)."""
     sg = {1024: 0, 512: 1, 2048: 2, 4096: 3}[int(sparse_grid)]
     dg = {2048: 0, 1024: 1, 4096: 2, 8192: 3}[int(dense_grid)]
-    return sg | (dg << 2) | (0 if premerge else 16) | (32 if giant_skip else 0)
+    return sg | (dg << 2) | (0 if premerge else 16) | (32 if giant_skip else 0) | (0 if tile_join else 64)
 
 
 def make_options(predicate: str = "fp32_filter", strict: bool = False, cell_factor: float = 0.0,

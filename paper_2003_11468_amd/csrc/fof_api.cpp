@@ -170,7 +170,7 @@ bool options_valid(const fof_options &o)
         return false;
     if (o.domains < 0 || o.domains > kMaxDomains) return false;
     if (o.link_order != 0 && o.link_order != 1) return false;
-    if (o.schedule < 0 || o.schedule >= 64) return false;
+    if (o.schedule < 0 || o.schedule >= 128) return false;
     if ((o.schedule & 32) && o.domains > 1) return false;   // the giant-component skip has no domain mode
     if (o.compression != 0 && o.compression != 1) return false;
     for (int k = 0; k < 2; ++k)
@@ -420,6 +420,7 @@ void carve(const fof_options &o, const Layout &p, const BoxDev &box0, void *ws, 
     d.premerge = (o.schedule & 16) ? 0 : 1;
     d.find_mode = o.compression;
     d.giant_skip = (o.schedule & 32) ? 1 : 0;
+    d.tile_join = (o.schedule & 64) ? 0 : 1;
     d.sample = 0;
     d.domains = o.domains > 1 ? o.domains : 0;
     d.link_random = o.link_order == 1 ? 1 : 0;

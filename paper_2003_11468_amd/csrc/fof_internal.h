@@ -58,7 +58,7 @@ struct Plan {
     int64_t n_tiles;        // input tiles of the bucket pass (2048 particles each)
     int32_t bucket_shift;   // bucket of a cell = cell >> bucket_shift
     int32_t n_buckets;      // at most 256
-    int32_t seg_shift;      // segment of a cell = cell >> seg_shift (6..14; a segment's counts fit in LDS)
+    int32_t seg_shift;      // segment of a cell = cell >> seg_shift (6..16; a segment's counts fit in LDS)
     int32_t sub_log2;       // segments per bucket = 1 << sub_log2 (bucket_shift - seg_shift, at most 10)
     int64_t n_segments;     // ceil(n_cells / 2^seg_shift)
     int32_t dense_min;      // cells with at least this many particles use the wave kernel
@@ -71,6 +71,7 @@ struct Plan {
     int32_t giant_skip;     // 1: Afforest-style linking (sampled axis links, then the rest skipping the
                             // largest group found)
     int32_t sample;         // set for the first pass of giant_skip: axis-neighbour cells only
+    int32_t tile_join;      // 1: the per-particle search joins the links inside its 64-particle tiles
     int64_t max_items;      // capacity of `items`
     int64_t max_edges;      // capacity of `edges`: kEdgeSlices slices of max_edges / kEdgeSlices
 

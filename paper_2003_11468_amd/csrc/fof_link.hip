@@ -103,6 +103,42 @@ __device__ __forceinline__ void merge_pair(const Plan &p, int a, int b, unsigned
     else retries += unite(p.parent, a, b, p.link_random, p.find_mode);
 }
 
+__device__ __forceinline__ int lds_ld(int *a) { return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ __forceinline__ void lds_st(int *a, int v)
+{
+    __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Root of sub-cell x in the LDS forest f (path halving; parents only point to
+// smaller indices).
+__device__ __forceinline__ int lds_find(int *f, int x)
+{
+    while (true) {
+        const int px = lds_ld(f + x);
+        if (px == x) return x;
+        const int gx = lds_ld(f + px);
+        if (gx == px) return px;
+        lds_st(f + x, gx);
+        x = gx;
+    }
+}
+
+__device__ __forceinline__ void lds_unite(int *f, int a, int b)
+{
+    while (true) {
+        a = lds_find(f, a);
+        b = lds_find(f, b);
+        if (a == b) return;
+        const int lo = min(a, b), hi = max(a, b);
+        int expected = hi;
+        if (__hip_atomic_compare_exchange_strong(f + hi, &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+        a = expected;
+        b = lo;
+    }
+}
+
 // --------------------------------------------------------- sparse (lane) --
 
 // Periodic shift code of one axis for a candidate range: 0 none; 1 the
@@ -215,9 +251,10 @@ constexpr int kMaxUnits = 64 * kMaxRanges;
 struct SparseLds {
     int start[kMaxUnits + 1];   // first pair of each unit (exclusive prefix)
     int j0[kMaxUnits];          // first candidate of each unit
-    int tag[kMaxUnits];         // shift code (bits 0-5) | home lane << 8
-    float4 home[64];            // the home particles
-    int2 ebuf[kEdgeBuf];        // edge sink buffer
+    unsigned short tag[kMaxUnits];   // shift code (bits 0-5) | home lane << 8
+    float4 home[64];                 // the home particles
+    int2 ebuf[kEdgeBuf];             // edge sink buffer
+    unsigned long long adj[64];      // links inside the tile: bit v of adj[u] for home u, slot s0 + v
 };
 
 // Box parameters of the pair test, in registers.
@@ -237,7 +274,7 @@ struct BoxPair {
 // home particle of the tile lies in one box, whose parameters are `bp`.
 template <bool kFP64, bool kStats, bool kOneBox>
 __device__ __forceinline__ void sparse_pairs(const Plan &p, SparseLds &L, EdgeSink &sink, int s0, int n_units,
-                                             int n_pairs, int b, BoxPair bp, unsigned long long &tests,
+                                             int n_pairs, int b, BoxPair bp, bool in_tile, unsigned long long &tests,
                                              unsigned long long &links, unsigned long long &band, unsigned &retries)
 {
     const int lane = lane_id();
@@ -317,7 +354,14 @@ __device__ __forceinline__ void sparse_pairs(const Plan &p, SparseLds &L, EdgeSi
                 if (kStats) ++tests;
                 if (kStats && link) ++links;
             }
-            sink.push(p, link, s0 + hl, jj[a], retries);
+            // a link inside the tile goes to the tile's bit matrix, the others to the edge list
+            const unsigned v = (unsigned)(jj[a] - s0);
+            const bool local = in_tile && v < 64u;
+            if (link && local) {   // both directions: the rows are then the tile's undirected links
+                atomicOr(&L.adj[hl], 1ull << v);
+                atomicOr(&L.adj[v & 63u], 1ull << hl);
+            }
+            sink.push(p, link && !local, s0 + hl, jj[a], retries);
         }
     }
 }
@@ -331,6 +375,15 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
     EdgeSink sink{L.ebuf, 0};
     unsigned long long tests = 0, links = 0, band = 0;
     unsigned retries = 0;
+    // links inside a tile are joined by the search itself (index order only:
+    // the hook goes under the smallest slot; not in domain mode, whose links
+    // across slabs must go through the boundary list)
+    const bool tile_union = p.tile_join != 0 && p.link_random == 0 && p.domains <= 1;
+    int hook_x = -1, hook_r = 0, hook_old = 0;   // this lane's last tile hook
+    auto check_hook = [&]() {
+        if (hook_x >= 0 && hook_old != hook_x) retries += 1 + unite(p.parent, hook_x, hook_r, false, p.find_mode);
+        hook_x = -1;
+    };
     const int64_t n_tiles = (p.n + 63) / 64;
     // each XCD sweeps one contiguous range of tiles, so the neighbour rows of
     // consecutive tiles are reused from its own L2
@@ -502,17 +555,53 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
             L.home[lane] = pi;
         }
         __builtin_amdgcn_wave_barrier();
+        check_hook();
+        L.adj[lane] = 0ull;
+        __builtin_amdgcn_wave_barrier();
         // a tile inside one box keeps that box's parameters in registers for
         // every pair; otherwise each pair reads the box of its home particle
+        const int s0 = (int)(tile * 64);
         const int b0 = __builtin_amdgcn_readfirstlane(b);
         if (__ballot(b != b0) == 0)
-            sparse_pairs<kFP64, kStats, true>(p, L, sink, (int)(tile * 64), n_units, n_pairs, b, BoxPair::of(box_of(p, b0)),
-                                              tests, links, band, retries);
+            sparse_pairs<kFP64, kStats, true>(p, L, sink, s0, n_units, n_pairs, b, BoxPair::of(box_of(p, b0)),
+                                              tile_union, tests, links, band, retries);
         else
-            sparse_pairs<kFP64, kStats, false>(p, L, sink, (int)(tile * 64), n_units, n_pairs, b, BoxPair{},
-                                               tests, links, band, retries);
+            sparse_pairs<kFP64, kStats, false>(p, L, sink, s0, n_units, n_pairs, b, BoxPair{}, tile_union, tests,
+                                               links, band, retries);
         __builtin_amdgcn_wave_barrier();
+        if (tile_union) {
+            // The components of the links inside the tile, by Warshall's
+            // closure over the rows of the bit matrix (one per lane): row u
+            // starts as u's links and u itself; for each slot k with links,
+            // every row that holds k takes in row k. Afterwards row u is u's
+            // component, and its lowest bit the component's smallest slot,
+            // the node of smallest hooking key, under which u is hooked.
+            // Every particle is still its own root while the search runs,
+            // unless a full edge-list slice made a search merge its surplus
+            // at once: so the hook is a compare-and-swap, and one that finds
+            // its slot hooked already becomes an ordinary union.
+            const unsigned long long tile_links = L.adj[lane];
+            unsigned long long todo = __ballot(tile_links != 0ull);
+            if (todo) {
+                unsigned long long row = tile_links | (1ull << lane);
+                while (todo) {
+                    const int k = __ffsll((long long)todo) - 1;
+                    todo &= todo - 1ull;
+                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)row, k);
+                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(row >> 32), k);
+                    if ((row >> k) & 1ull) row |= ((unsigned long long)hi << 32) | lo;
+                }
+                const int r = __ffsll((long long)row) - 1;
+                if (r != lane) {   // read back with the next tile, so the wave does not wait for it
+                    hook_x = s0 + lane;
+                    hook_r = s0 + r;
+                    hook_old = atomicCAS(p.parent + hook_x, hook_x, hook_r);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
     }
+    check_hook();
     sink.flush(p, retries);
     if (kStats) {
         tests = wave_sum_u64(tests);
@@ -982,42 +1071,6 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
 // link them) and each dense cell has one wavefront, so the hooks are plain
 // stores.
 constexpr int kMaxSub = 512;
-
-__device__ __forceinline__ int lds_ld(int *a) { return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
-__device__ __forceinline__ void lds_st(int *a, int v)
-{
-    __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Root of sub-cell x in the LDS forest f (path halving; parents only point to
-// smaller indices).
-__device__ __forceinline__ int lds_find(int *f, int x)
-{
-    while (true) {
-        const int px = lds_ld(f + x);
-        if (px == x) return x;
-        const int gx = lds_ld(f + px);
-        if (gx == px) return px;
-        lds_st(f + x, gx);
-        x = gx;
-    }
-}
-
-__device__ __forceinline__ void lds_unite(int *f, int a, int b)
-{
-    while (true) {
-        a = lds_find(f, a);
-        b = lds_find(f, b);
-        if (a == b) return;
-        const int lo = min(a, b), hi = max(a, b);
-        int expected = hi;
-        if (__hip_atomic_compare_exchange_strong(f + hi, &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
-            return;
-        a = expected;
-        b = lo;
-    }
-}
 
 __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
 {

@@ -11,7 +11,8 @@ Cell size and tile shape:
 - segment_log2: cells per work-group of the in-LDS cell sort (0: automatic).
 Work schedule and contention variants:
 - schedule: work-groups of the two persistent link kernels, whether dense
-  cells are pre-merged by sub-cells, and the giant-component skip
+  cells are pre-merged by sub-cells, the giant-component skip, and whether
+  the per-particle search joins the links inside its tiles
   (fof_options.schedule);
 - link_order: hook by index or by a pseudo-random priority (paper, Section 3.2);
 - compression: path halving or compression of paths of length >= 2 only
@@ -44,7 +45,8 @@ DENSE_MINS = (8, 16, 32)
 AXES = {
     "schedule": tuple(schedule_bits(sg, dg, pm) for sg, dg, pm in
                       ((1024, 2048, True), (2048, 2048, True), (512, 2048, True), (1024, 4096, True),
-                       (1024, 1024, True), (1024, 2048, False))) + (schedule_bits(giant_skip=True),),
+                       (1024, 1024, True), (1024, 2048, False))) + (schedule_bits(giant_skip=True),
+                                                                     schedule_bits(tile_join=False)),
     "link_order": ("index", "random"),
     "compression": ("halving", "depth2"),
     "segment_log2": (0, 13, 14, 16),

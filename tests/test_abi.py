@@ -67,7 +67,9 @@ def test_create_rejects_bad_options():
         fof.fof_create(o)
     assert e.value.status == fof.FOF_ERR_INVALID_ARG
     fof.fof_destroy(fof.fof_create(fof.make_options(schedule=fof.schedule_bits(giant_skip=True))))
-    for field, bad in (("schedule", 64), ("schedule", -1), ("compression", 2), ("compression", -1)):
+    fof.fof_destroy(fof.fof_create(fof.make_options(schedule=fof.schedule_bits(tile_join=False))))
+    assert fof.schedule_bits(tile_join=False) == 64
+    for field, bad in (("schedule", 128), ("schedule", -1), ("compression", 2), ("compression", -1)):
         o = fof.fof_default_options()
         setattr(o, field, bad)
         with pytest.raises(fof.FoFError) as e:

@@ -592,7 +592,8 @@ def test_autotuner_choice_is_exact(tmp_path):
 
 TUNER_OPTIONS = ([dict(schedule=fof.schedule_bits(sg, dg, pm)) for sg, dg, pm in
                   ((512, 1024, True), (2048, 4096, True), (4096, 8192, True), (1024, 2048, False))] +
-                 [dict(schedule=fof.schedule_bits(giant_skip=True)),
+                 [dict(schedule=fof.schedule_bits(tile_join=False)),
+                  dict(schedule=fof.schedule_bits(giant_skip=True)),
                   dict(schedule=fof.schedule_bits(giant_skip=True), link_order="random", compression="depth2"),
                   dict(link_order="random"), dict(compression="depth2"),
                   dict(compression="depth2", link_order="random"), dict(segment_log2=12)])
