@@ -187,6 +187,11 @@ def parse():
     ap.add_argument("--cell-factor", type=float, default=None, help="skip tuning, use this cell size")
     ap.add_argument("--dense-min", type=int, default=None, help="skip tuning, use this dense threshold")
     ap.add_argument("--schedule", type=int, default=0, help="with --cell-factor and --dense-min: fof_options.schedule")
+    ap.add_argument("--link-order", default="index", choices=("index", "random"),
+                    help="with --cell-factor and --dense-min: hooking order")
+    ap.add_argument("--compression", default="halving", choices=("halving", "depth2"),
+                    help="with --cell-factor and --dense-min: path compression of the finds")
+    ap.add_argument("--segment-log2", type=int, default=0, help="with --cell-factor and --dense-min: cell sort segments")
     ap.add_argument("--no-side", action="store_true", help="only the headline workload")
     ap.add_argument("--no-large", action="store_true", help="no 134M and 1.07B side workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -256,6 +261,7 @@ def choose(tune, pos, w, predicate, args, **kw):
     given on the command line."""
     if args.cell_factor is not None and args.dense_min is not None:
         return {"cell_factor": args.cell_factor, "dense_min": args.dense_min, "schedule": args.schedule,
+                "link_order": args.link_order, "compression": args.compression, "segment_log2": args.segment_log2,
                 "tuned": False}
     t0 = time.perf_counter()
     r = tune.autotune(pos, w.offsets, w.box, w.lx, predicate, cache_path=None, repeats=2, **kw)
