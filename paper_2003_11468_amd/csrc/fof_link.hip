@@ -123,6 +123,23 @@ __device__ __forceinline__ int lds_find(int *f, int x)
     }
 }
 
+// Warshall's closure of 64 boolean rows, one per lane (bit v of lane u's row:
+// u is joined to v; every row holds its own bit): for each k in `todo` (the
+// lanes whose rows hold other bits), every row holding bit k takes in row k,
+// read with readlane. Afterwards a row is its lane's component, so its lowest
+// bit is the component's smallest member. No branch and no memory access.
+__device__ __forceinline__ unsigned long long close_rows(unsigned long long row, unsigned long long todo)
+{
+    while (todo) {
+        const int k = __ffsll((long long)todo) - 1;
+        todo &= todo - 1ull;
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)row, k);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(row >> 32), k);
+        if ((row >> k) & 1ull) row |= ((unsigned long long)hi << 32) | lo;
+    }
+    return row;
+}
+
 __device__ __forceinline__ void lds_unite(int *f, int a, int b)
 {
     while (true) {
@@ -320,6 +337,15 @@ __device__ __forceinline__ void sparse_pairs(const Plan &p, SparseLds &L, EdgeSi
 #pragma unroll
         for (int a = 0; a < kAhead; ++a)
             if (lv[a]) cc[a] = p.sorted[jj[a]];
+        // no lane's pairs of these steps need a periodic shift (the common
+        // case away from the box faces): plain differences, the same values
+        bool plain = false;
+        if constexpr (!kFP64) {
+            int codes = 0;
+#pragma unroll
+            for (int a = 0; a < kAhead; ++a) codes |= tg[a];
+            plain = __ballot((codes & 63) != 0) == 0;
+        }
 #pragma unroll
         for (int a = 0; a < kAhead; ++a) {
             const int hl = tg[a] >> 8, code = tg[a] & 63;
@@ -340,9 +366,16 @@ __device__ __forceinline__ void sparse_pairs(const Plan &p, SparseLds &L, EdgeSi
                     const double r2 = sxy + tz * tz;
                     link = strict ? (r2 < bx.l2) : (r2 <= bx.l2);
                 } else {
-                    const float dx = axis_diff(hp.x, c.x, code & 3, bx.L32);
-                    const float dy = axis_diff(hp.y, c.y, (code >> 2) & 3, bx.L32);
-                    const float dz = axis_diff(hp.z, c.z, (code >> 4) & 3, bx.L32);
+                    float dx, dy, dz;
+                    if (plain) {
+                        dx = hp.x - c.x;
+                        dy = hp.y - c.y;
+                        dz = hp.z - c.z;
+                    } else {
+                        dx = axis_diff(hp.x, c.x, code & 3, bx.L32);
+                        dy = axis_diff(hp.y, c.y, (code >> 2) & 3, bx.L32);
+                        dz = axis_diff(hp.z, c.z, (code >> 4) & 3, bx.L32);
+                    }
                     const float rr = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                     if (rr < bx.lo32) link = true;
                     else if (rr > bx.hi32) link = false;
@@ -581,16 +614,9 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
             // at once: so the hook is a compare-and-swap, and one that finds
             // its slot hooked already becomes an ordinary union.
             const unsigned long long tile_links = L.adj[lane];
-            unsigned long long todo = __ballot(tile_links != 0ull);
+            const unsigned long long todo = __ballot(tile_links != 0ull);
             if (todo) {
-                unsigned long long row = tile_links | (1ull << lane);
-                while (todo) {
-                    const int k = __ffsll((long long)todo) - 1;
-                    todo &= todo - 1ull;
-                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)row, k);
-                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(row >> 32), k);
-                    if ((row >> k) & 1ull) row |= ((unsigned long long)hi << 32) | lo;
-                }
+                const unsigned long long row = close_rows(tile_links | (1ull << lane), todo);
                 const int r = __ffsll((long long)row) - 1;
                 if (r != lane) {   // read back with the next tile, so the wave does not wait for it
                     hook_x = s0 + lane;
@@ -1133,22 +1159,53 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
                 n_used += __popcll(m);
             }
             __builtin_amdgcn_wave_barrier();
-            for (int q = lane; q < n_used; q += 64) {
-                const int t = ul[q];
-                const int sx = t % k, sy = (t / k) % k, sz = t / (k * k);
-                for (int o = 14; o < 27; ++o) {
-                    const int ux = sx + o % 3 - 1, uy = sy + (o / 3) % 3 - 1, uz = sz + o / 9 - 1;
-                    if (ux < 0 || ux >= k || uy < 0 || uy >= k || uz >= k) continue;
-                    const int u = (uz * k + uy) * k + ux;
-                    if (rp[u] != kEmpty) lds_unite(jf, t, u);
+            if (n_used <= 64) {
+                // at most 64 occupied sub-cells: lane q holds a row of bits, the
+                // listed sub-cells touching sub-cell ul[q], and the components
+                // come from the closure of the rows; jf maps a listed sub-cell
+                // to its place in the list, then to its component's first one
+                if (lane < n_used) jf[ul[lane]] = lane;
+                __builtin_amdgcn_wave_barrier();
+                unsigned long long row = 0ull;
+                int t = 0;
+                if (lane < n_used) {
+                    t = ul[lane];
+                    const int sx = t % k, sy = (t / k) % k, sz = t / (k * k);
+                    row = 1ull << lane;
+#pragma unroll
+                    for (int o = 0; o < 27; ++o) {   // no branch: an outside neighbour reads sub-cell t
+                        const int ux = sx + o % 3 - 1, uy = sy + (o / 3) % 3 - 1, uz = sz + o / 9 - 1;
+                        const bool in = (unsigned)ux < (unsigned)k && (unsigned)uy < (unsigned)k &&
+                                        (unsigned)uz < (unsigned)k;
+                        const int u = in ? (uz * k + uy) * k + ux : t;
+                        row |= (rp[u] != kEmpty ? 1ull : 0ull) << jf[u];
+                    }
                 }
-            }
-            __builtin_amdgcn_wave_barrier();
-            // the particle of smallest key of each joined set, at its root sub-cell
-            for (int q = lane; q < n_used; q += 64) {
-                const int t = ul[q];
-                const int r = lds_find(jf, t);
-                if (r != t) atomicMin(&rp[r], rp[t]);
+                row = close_rows(row, __ballot(lane < n_used && row != (1ull << lane)));
+                __builtin_amdgcn_wave_barrier();   // every map entry read
+                if (lane < n_used) {
+                    const int rt = ul[__ffsll((long long)row) - 1];
+                    jf[t] = rt;
+                    if (rt != t) atomicMin(&rp[rt], rp[t]);
+                }
+            } else {
+                for (int q = lane; q < n_used; q += 64) {
+                    const int t = ul[q];
+                    const int sx = t % k, sy = (t / k) % k, sz = t / (k * k);
+                    for (int o = 14; o < 27; ++o) {
+                        const int ux = sx + o % 3 - 1, uy = sy + (o / 3) % 3 - 1, uz = sz + o / 9 - 1;
+                        if (ux < 0 || ux >= k || uy < 0 || uy >= k || uz >= k) continue;
+                        const int u = (uz * k + uy) * k + ux;
+                        if (rp[u] != kEmpty) lds_unite(jf, t, u);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                // the particle of smallest key of each joined set, at its root sub-cell
+                for (int q = lane; q < n_used; q += 64) {
+                    const int t = ul[q];
+                    const int r = lds_find(jf, t);
+                    if (r != t) atomicMin(&rp[r], rp[t]);
+                }
             }
             __builtin_amdgcn_wave_barrier();
         }
