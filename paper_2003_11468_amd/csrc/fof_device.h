@@ -36,6 +36,29 @@ __device__ __forceinline__ int find_box_wave(const int64_t *p0, int n_boxes, int
     return find_box(p0, n_boxes, i);
 }
 
+// The box a wave looked up last, with its slot range (uniform across the
+// wave): lookups that stay inside it skip the binary search.
+struct BoxHint {
+    int b = 0;
+    int64_t lo = 0, hi = 0;
+};
+
+// find_box_wave with a hint: the first active lane's box is searched for only
+// when it lies outside the hinted box, which it then replaces.
+__device__ __forceinline__ int find_box_hint(const int64_t *p0, int n_boxes, int64_t i, BoxHint &h)
+{
+    const unsigned lo32 = __builtin_amdgcn_readfirstlane((unsigned)(uint64_t)i);
+    const unsigned hi32 = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)i >> 32));
+    const int64_t i0 = (int64_t)(((uint64_t)hi32 << 32) | lo32);
+    if (!(i0 >= h.lo && i0 < h.hi)) {
+        h.b = find_box(p0, n_boxes, i0);
+        h.lo = p0[h.b];
+        h.hi = p0[h.b + 1];
+    }
+    if (i >= h.lo && i < h.hi) return h.b;
+    return find_box(p0, n_boxes, i);
+}
+
 // Cell coordinate along one axis: floor(x * nc / L) clamped to [0, nc - 1].
 // The product is formed in double, so for L = 1 it is exact; a NaN lands in
 // cell 0 (the coordinate error is latched separately).

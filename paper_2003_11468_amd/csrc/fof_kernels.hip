@@ -80,9 +80,10 @@ __global__ void __launch_bounds__(kBlock) k_clear(Plan p)
 
 // Cell key of input particle i; `ok` tells whether its coordinates are finite
 // and inside [0, L).
-__device__ __forceinline__ int64_t input_key(const Plan &p, int64_t i, float &x, float &y, float &z, bool &ok)
+__device__ __forceinline__ int64_t input_key(const Plan &p, int64_t i, float &x, float &y, float &z, bool &ok,
+                                             BoxHint &hint)
 {
-    const int b = p.n_boxes == 1 ? 0 : find_box_wave(p.box_p0, p.n_boxes, i);
+    const int b = p.n_boxes == 1 ? 0 : find_box_hint(p.box_p0, p.n_boxes, i, hint);
     const BoxDev &bd = box_of(p, b);
     x = p.pos[3 * i + 0];
     y = p.pos[3 * i + 1];
@@ -94,6 +95,7 @@ __device__ __forceinline__ int64_t input_key(const Plan &p, int64_t i, float &x,
 // Bucket histogram of one tile, written bucket-major: hist[b * n_tiles + tile].
 __global__ void __launch_bounds__(kBlock) k_bucket_hist(Plan p)
 {
+    BoxHint hint;
     __shared__ int cnt[kMaxBuckets];
     const int64_t tile = blockIdx.x;
     for (int b = threadIdx.x; b < kMaxBuckets; b += kBlock) cnt[b] = 0;
@@ -105,7 +107,7 @@ __global__ void __launch_bounds__(kBlock) k_bucket_hist(Plan p)
         if (i < p.n) {
             float x, y, z;
             bool ok;
-            const int64_t key = input_key(p, i, x, y, z, ok);
+            const int64_t key = input_key(p, i, x, y, z, ok, hint);
             bad |= !ok;
             atomicAdd(&cnt[(int)(key >> p.bucket_shift)], 1);
         }
@@ -119,6 +121,7 @@ __global__ void __launch_bounds__(kBlock) k_bucket_hist(Plan p)
 // the staging order (x, y, z, original index as bits); stpos[i] = staging slot.
 __global__ void __launch_bounds__(kBlock) k_bucket_scatter(Plan p)
 {
+    BoxHint hint;
     __shared__ float4 stage[kSortTile];
     __shared__ unsigned char stage_b[kSortTile];
     __shared__ int cnt[kMaxBuckets], first[kMaxBuckets], dst0[kMaxBuckets];
@@ -139,7 +142,7 @@ __global__ void __launch_bounds__(kBlock) k_bucket_scatter(Plan p)
         if (i < p.n) {
             float x, y, z;
             bool ok;
-            const int64_t key = input_key(p, i, x, y, z, ok);
+            const int64_t key = input_key(p, i, x, y, z, ok, hint);
             bk[k] = (int)(key >> p.bucket_shift);
             rk[k] = atomicAdd(&cnt[bk[k]], 1);
             v[k] = make_float4(x, y, z, __int_as_float((int)i));
@@ -241,9 +244,9 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(ScanArgs a)
 // ---------------------------------------------------------- segment pass --
 
 // Cell of a staged particle (x, y, z, original index as bits).
-__device__ __forceinline__ int64_t staged_cell(const Plan &p, const float4 &v)
+__device__ __forceinline__ int64_t staged_cell(const Plan &p, const float4 &v, BoxHint &hint)
 {
-    const int b = p.n_boxes == 1 ? 0 : find_box_wave(p.box_p0, p.n_boxes, __float_as_int(v.w));
+    const int b = p.n_boxes == 1 ? 0 : find_box_hint(p.box_p0, p.n_boxes, __float_as_int(v.w), hint);
     return particle_cell(box_of(p, b), v.x, v.y, v.z);
 }
 
@@ -280,6 +283,7 @@ constexpr int kMaxSubs = 1 << kMaxSubLog2;
 // Segment histogram of one tile (LDS), added to the global segment counts.
 __global__ void __launch_bounds__(kBlock) k_seg_hist(Plan p)
 {
+    BoxHint hint;
     __shared__ int cnt[kMaxSubs];
     __shared__ int info[3], lds[kBlock / 64];
     int lo, hi;
@@ -290,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_hist(Plan p)
     for (int s = threadIdx.x; s < subs; s += kBlock) cnt[s] = 0;
     __syncthreads();
     for (int k = lo + (int)threadIdx.x; k < hi; k += kBlock)
-        atomicAdd(&cnt[(int)(staged_cell(p, p.staging[k]) >> p.seg_shift) - seg0], 1);
+        atomicAdd(&cnt[(int)(staged_cell(p, p.staging[k], hint) >> p.seg_shift) - seg0], 1);
     __syncthreads();
     for (int s = threadIdx.x; s < subs; s += kBlock)
         if (cnt[s]) atomicAdd(p.seg_end + seg0 + s, cnt[s]);
@@ -300,6 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_hist(Plan p)
 // segment's cursor (seg_end: start before, end after this pass).
 __global__ void __launch_bounds__(kBlock) k_seg_scatter(Plan p)
 {
+    BoxHint hint;
     __shared__ float4 stage[kSortTile];
     __shared__ int stage_k[kSortTile];
     __shared__ unsigned short stage_s[kSortTile];
@@ -320,7 +325,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_scatter(Plan p)
         sb[q] = -1;
         if (k < hi) {
             v[q] = p.staging[k];
-            sb[q] = (int)(staged_cell(p, v[q]) >> p.seg_shift) - seg0;
+            sb[q] = (int)(staged_cell(p, v[q], hint) >> p.seg_shift) - seg0;
             rk[q] = atomicAdd(&cnt[sb[q]], 1);
         }
     }
@@ -405,6 +410,7 @@ static_assert(kCntCap >= kOrderCap, "a segment placed through LDS is one window"
 template <int kWordsMax>
 __global__ void __launch_bounds__(kSegBlock) __attribute__((amdgpu_waves_per_eu(kWordsMax <= 1024 ? 8 : 6))) k_cell_sort(Plan p)
 {
+    BoxHint hint;
     constexpr int kWordsPerThread = (kWordsMax + kSegBlock - 1) / kSegBlock;
     static_assert(kWordsMax % kSegBlock == 0 || kWordsMax < kSegBlock, "whole words per thread");
     __shared__ int cnt[kCntCap];                     // per occupied cell of a window: count, start, cursor
@@ -427,7 +433,7 @@ __global__ void __launch_bounds__(kSegBlock) __attribute__((amdgpu_waves_per_eu(
     // the segment's cell of a staged particle; a cell outside the segment
     // cannot happen with a consistent partition and is latched, not used
     auto local_cell = [&](const float4 &v) {
-        const int64_t c = staged_cell(p, v) - cell0;
+        const int64_t c = staged_cell(p, v, hint) - cell0;
         if ((uint64_t)c >= (uint64_t)seg_cells) {
             bad = true;
             return 0;

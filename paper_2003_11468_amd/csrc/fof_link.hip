@@ -412,6 +412,7 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
     // the hook goes under the smallest slot; not in domain mode, whose links
     // across slabs must go through the boundary list)
     const bool tile_union = p.tile_join != 0 && p.link_random == 0 && p.domains <= 1;
+    BoxHint hint;   // consecutive tiles of a wave nearly always lie in one box
     int hook_x = -1, hook_r = 0, hook_old = 0;   // this lane's last tile hook
     auto check_hook = [&]() {
         if (hook_x >= 0 && hook_old != hook_x) retries += 1 + unite(p.parent, hook_x, hook_r, false, p.find_mode);
@@ -428,7 +429,7 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
         int b = 0;
         if (s64 < p.n) {
             const int s = (int)s64;
-            b = p.n_boxes == 1 ? 0 : find_box_wave(p.box_p0, p.n_boxes, s64);
+            b = p.n_boxes == 1 ? 0 : find_box_hint(p.box_p0, p.n_boxes, s64, hint);
             const BoxDev &bd = box_of(p, b);
             pi = p.sorted[s];
             const int nc = bd.nc;
@@ -1393,6 +1394,7 @@ __global__ void __launch_bounds__(kBlock) k_link_rest(Plan p)
     unsigned retries = 0;
     const bool rnd = p.link_random != 0;
     const bool strict = p.strict != 0;
+    BoxHint hint;
     const int64_t n_tiles = (p.n + 63) / 64;
     const XcdRange xr = xcd_range(n_tiles, kWaves, wid);
     for (int64_t tile = xr.first; tile < xr.end; tile += xr.stride) {
@@ -1401,12 +1403,12 @@ __global__ void __launch_bounds__(kBlock) k_link_rest(Plan p)
         const int s = active ? (int)s64 : 0;
         const int g = find_root(p.parent, p.counters->giant, p.find_mode, rnd);
         if (active) active = find_root(p.parent, s, p.find_mode, rnd) != g;
-        int b = 0, cx = 0, cy = 0, cz = 0, nc = 3;
+        int cx = 0, cy = 0, cz = 0, nc = 3;
         int64_t cb = 0;
         float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
         BoxPair bx{};
+        const int b = p.n_boxes == 1 ? 0 : find_box_hint(p.box_p0, p.n_boxes, s, hint);
         if (active) {
-            b = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, s);
             const BoxDev &bd = box_of(p, b);
             bx = BoxPair::of(bd);
             h = p.sorted[s];
