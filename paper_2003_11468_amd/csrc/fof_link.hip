@@ -645,7 +645,7 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
     }
 }
 
-constexpr int kUnionIlp = 4;   // queued pairs a lane merges at once
+constexpr int kUnionIlp = 8;   // queued pairs a lane merges at once
 
 // Merges the queued pairs, no ordering needed. Each lane carries kUnionIlp
 // pairs at once: the finds of their 2 kUnionIlp end points advance together,
