@@ -693,49 +693,73 @@ __global__ void __launch_bounds__(kBlock) k_find_depth(Plan p)
 // worst case) then come to one pair per wave instead of one per 64 particles.
 __global__ void __launch_bounds__(kBlock) k_flatten(Plan p)
 {
+    constexpr int kFlatIlp = 4;   // stretches whose chases advance together
     const int lane = lane_id();
     int pend_key = -1, pend_m = INT_MAX, pend_c = 0;   // the same in every lane
-    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < p.n; base += (int64_t)gridDim.x * kBlock) {
-        const int64_t s64 = base + threadIdx.x;
-        int root_key = -1, m = INT_MAX, c = 0;
-        if (s64 < p.n) {
-            const int s = (int)s64;
-            int r = s, q = p.parent[s];
-            while (q != r) {
-                r = q;
-                q = p.parent[r];
-            }
-            if (r != s) {
-                p.parent[s] = r;
-                root_key = r;
-                m = p.orig[s];
-                c = 1;
-            }
+    const int64_t stretch = (int64_t)gridDim.x * kBlock;
+    for (int64_t base0 = (int64_t)blockIdx.x * kBlock; base0 < p.n; base0 += kFlatIlp * stretch) {
+        // the roots of this thread's particle in each of kFlatIlp stretches
+        int r[kFlatIlp], q[kFlatIlp];
+        bool live[kFlatIlp];
+#pragma unroll
+        for (int u = 0; u < kFlatIlp; ++u) {
+            const int64_t s64 = base0 + u * stretch + threadIdx.x;
+            live[u] = s64 < p.n;
+            r[u] = live[u] ? (int)s64 : 0;
         }
-        const int prev = __shfl_up(root_key, 1, 64);
-        const unsigned long long heads = __ballot(lane == 0 || prev != root_key);
-        const int last_head = 63 - __clzll((long long)heads);   // first lane of the run holding lane 63
-        const int key_first = __shfl(root_key, 0, 64), key_last = __shfl(root_key, 63, 64);
-        const bool head = wave_runs_min_add(root_key, m, c);
-        if (pend_key >= 0) {
-            if (pend_key == key_first) {
-                if (lane == 0) {   // lane 0 heads the first run
-                    m = min(m, pend_m);
-                    c += pend_c;
+#pragma unroll
+        for (int u = 0; u < kFlatIlp; ++u) q[u] = p.parent[r[u]];
+        while (true) {
+            bool more = false;
+#pragma unroll
+            for (int u = 0; u < kFlatIlp; ++u) more = more || q[u] != r[u];
+            if (!more) break;
+#pragma unroll
+            for (int u = 0; u < kFlatIlp; ++u)
+                if (q[u] != r[u]) r[u] = q[u];
+#pragma unroll
+            for (int u = 0; u < kFlatIlp; ++u) q[u] = p.parent[r[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kFlatIlp; ++u) {
+            const int64_t base = base0 + u * stretch;
+            if (base >= p.n) break;   // uniform: later stretches are past the end too
+            const int64_t s64 = base + threadIdx.x;
+            int root_key = -1, m = INT_MAX, c = 0;
+            if (live[u]) {
+                const int s = (int)s64;
+                if (r[u] != s) {
+                    p.parent[s] = r[u];
+                    root_key = r[u];
+                    m = p.orig[s];
+                    c = 1;
                 }
-            } else if (lane == 0) {
-                atomicMin(&p.gmin[pend_key], pend_m);
-                atomicAdd(&p.gsize[pend_key], pend_c);
             }
+            const int prev = __shfl_up(root_key, 1, 64);
+            const unsigned long long heads = __ballot(lane == 0 || prev != root_key);
+            const int last_head = 63 - __clzll((long long)heads);   // first lane of the run holding lane 63
+            const int key_first = __shfl(root_key, 0, 64), key_last = __shfl(root_key, 63, 64);
+            const bool head = wave_runs_min_add(root_key, m, c);
+            if (pend_key >= 0) {
+                if (pend_key == key_first) {
+                    if (lane == 0) {   // lane 0 heads the first run
+                        m = min(m, pend_m);
+                        c += pend_c;
+                    }
+                } else if (lane == 0) {
+                    atomicMin(&p.gmin[pend_key], pend_m);
+                    atomicAdd(&p.gsize[pend_key], pend_c);
+                }
+            }
+            const int lm = __shfl(m, last_head, 64), lc = __shfl(c, last_head, 64);
+            if (head && lane != last_head) {
+                atomicMin(&p.gmin[root_key], m);
+                atomicAdd(&p.gsize[root_key], c);
+            }
+            pend_key = key_last;
+            pend_m = lm;
+            pend_c = lc;
         }
-        const int lm = __shfl(m, last_head, 64), lc = __shfl(c, last_head, 64);
-        if (head && lane != last_head) {
-            atomicMin(&p.gmin[root_key], m);
-            atomicAdd(&p.gsize[root_key], c);
-        }
-        pend_key = key_last;
-        pend_m = lm;
-        pend_c = lc;
     }
     if (pend_key >= 0 && lane == 0) {
         atomicMin(&p.gmin[pend_key], pend_m);
