@@ -58,7 +58,7 @@ struct Layout {
     // workspace layout (byte offsets)
     size_t o_boxes = 0, o_p0 = 0, o_counters = 0, o_groups = 0, o_cell = 0, o_part = 0, o_kmap = 0, o_sorted = 0,
            o_orig = 0, o_gmin = 0, o_parent = 0, o_gsize = 0, o_items = 0, o_edges = 0, o_hist = 0, o_staging = 0,
-           o_stpos = 0, o_wave_roots = 0, o_occ = 0, o_edge_fill = 0, o_seg = 0, o_staging2 = 0,
+           o_stpos = 0, o_wave_roots = 0, o_tile_dense = 0, o_occ = 0, o_edge_fill = 0, o_seg = 0, o_staging2 = 0,
            o_stage2_k = 0, o_bnd = 0, total = 0;
 };
 
@@ -350,6 +350,7 @@ fof_status make_layout(const fof_options &o, int64_t n_total, int64_t cells, int
     p.o_staging = take(sizeof(float) * 4 * n);
     p.o_stpos = take(sizeof(int32_t) * n);
     p.o_wave_roots = take(sizeof(int32_t) * ((n + 63) / 64));
+    p.o_tile_dense = take(sizeof(unsigned long long) * ((n + 63) / 64));
     p.o_occ = take(sizeof(uint2) * (((size_t)p.n_segments << (p.seg_shift - 5)) + 2));
     p.o_seg = take(sizeof(int32_t) * (size_t)p.n_segments);
     p.o_staging2 = take(sizeof(float) * 4 * n);
@@ -446,6 +447,7 @@ void carve(const fof_options &o, const Layout &p, const BoxDev &box0, void *ws, 
     d.staging = at<float4>(ws, p.o_staging);
     d.stpos = at<int32_t>(ws, p.o_stpos);
     d.wave_roots = at<int32_t>(ws, p.o_wave_roots);
+    d.tile_dense = at<unsigned long long>(ws, p.o_tile_dense);
     d.occ = at<uint2>(ws, p.o_occ);
     d.seg_end = at<int32_t>(ws, p.o_seg);
     d.staging2 = at<float4>(ws, p.o_staging2);

@@ -95,6 +95,7 @@ struct Plan {
                             // after cell 32w. Cell c starts at sorted slot
                             // cstart[occ[c/32].y + (occupied cells of that word below c)]
     int32_t *wave_roots;    // [n_waves] roots among the 64 sorted slots of each wave (resolve)
+    unsigned long long *tile_dense;   // [n_waves] bit l: sorted slot 64 w + l lies in a dense cell
     int64_t n_waves;
     int32_t *kmap;          // [n] staging slot of each sorted slot
     float4 *sorted;         // [n] cell-sorted x, y, z

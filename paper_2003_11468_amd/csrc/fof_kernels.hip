@@ -58,6 +58,7 @@ __global__ void __launch_bounds__(kBlock) k_clear(Plan p)
 {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < p.n_segments; i += stride) p.seg_end[i] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < p.n_waves; i += stride) p.tile_dense[i] = 0ull;
     int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < p.n_boxes) p.n_groups[t] = 0;
     if (t < kEdgeSlices) p.edge_fill[t] = 0;
@@ -576,6 +577,13 @@ __global__ void __launch_bounds__(kSegBlock) __attribute__((amdgpu_waves_per_eu(
                         const int cx = (int)(local % nc), cy = (int)((local / nc) % nc), cz = (int)(local / (nc * nc));
                         for (int q = 0; q < v; q += 64, ++slot)
                             if (slot < p.max_items) p.items[slot] = make_int4(cx | (cy << 16), start + q, bx, cz);
+                        // the cell's slots, in the masks by which the per-particle search skips dense tiles
+                        for (int s0 = start; s0 < start + v;) {
+                            const int lo = s0 & 63, hi = min(64, lo + (start + v - s0));
+                            const unsigned long long m = (hi == 64 ? ~0ull : (1ull << hi) - 1ull) & ~((1ull << lo) - 1ull);
+                            atomicOr(&p.tile_dense[s0 >> 6], m);
+                            s0 += hi - lo;
+                        }
                     }
                 }
             }
@@ -995,6 +1003,7 @@ int64_t sort_tiles_for(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 hipError_t launch_clear(const Plan &p, hipStream_t stream, KernelTimer *t)
 {
     int64_t work = p.n_segments > p.n_boxes ? p.n_segments : p.n_boxes;
+    if (work < p.n_waves) work = p.n_waves;
     if (work < kEdgeSlices) work = kEdgeSlices;
     unsigned g = grid_for(work);
     if (g > 65536u) g = 65536u;

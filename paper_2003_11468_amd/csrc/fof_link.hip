@@ -413,6 +413,7 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
     // across slabs must go through the boundary list)
     const bool tile_union = p.tile_join != 0 && p.link_random == 0 && p.domains <= 1;
     BoxHint hint;   // consecutive tiles of a wave nearly always lie in one box
+    const bool any_dense = p.counters->n_items != 0;
     int hook_x = -1, hook_r = 0, hook_old = 0;   // this lane's last tile hook
     auto check_hook = [&]() {
         if (hook_x >= 0 && hook_old != hook_x) retries += 1 + unite(p.parent, hook_x, hook_r, false, p.find_mode);
@@ -423,6 +424,13 @@ __global__ void __launch_bounds__(kBlock) k_link_sparse(Plan p)
     // consecutive tiles are reused from its own L2
     const XcdRange xr = xcd_range(n_tiles, kWaves, wid);
     for (int64_t tile = xr.first; tile < xr.end; tile += xr.stride) {
+        // a tile whose slots all lie in dense cells has nothing to search here
+        // (slots past the end count as dense)
+        if (any_dense) {
+            const int64_t left = p.n - tile * 64;
+            const unsigned long long dm = p.tile_dense[tile] | (left < 64 ? ~0ull << left : 0ull);
+            if (dm == ~0ull) continue;
+        }
         const int64_t s64 = tile * 64 + lane;
         Span R[kMaxRanges];   // own cell, next cell, then two per neighbour row
         float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
