@@ -172,6 +172,28 @@ def test_dense_and_sparse_kernels(dense_min, predicate):
         assert_single(pos, synth.linking_length(b, n), predicate=predicate, cell_factor=cf, dense_min=dense_min)
 
 
+# More links between tiles than the edge list holds (2^20 queued pairs at
+# this size): the per-particle search merges the surplus at once while other
+# tiles hook their own links, so some tile hooks find their slot hooked
+# already and fall back to an ordinary union. Both tile-join settings.
+@pytest.mark.parametrize("tile_join", [True, False])
+def test_edge_list_overflow_with_tile_join(tile_join):
+    n = 120000
+    pos = synth.clustered(n, 17, 0, 0.7)
+    lx = synth.linking_length(0.5, n)
+    ref = oracle.fof(pos, lx, 1.0)
+    f = fof.FoF("fp32_filter", cell_factor=1.0, stats=True, dense_min=1 << 30,
+                schedule=fof.schedule_bits(tile_join=tile_join))
+    try:
+        label, size, ng = f.run(torch.from_numpy(pos).cuda(), [0, n], 1.0, lx)
+        st = f.stats()
+        assert st["queued_links"] > (1 << 20)   # the list overflowed
+        assert np.array_equal(label.cpu().numpy(), ref[0]) and np.array_equal(size.cpu().numpy(), ref[1])
+        assert int(ng[0]) == ref[2]
+    finally:
+        f.close()
+
+
 @pytest.mark.parametrize("dense_min", [1, 1 << 30])
 def test_kernel_paths_on_hand_cases(dense_min):
     fx = load_fixture("fig2_indirect_u.txt")
