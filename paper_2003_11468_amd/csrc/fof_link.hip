@@ -1151,8 +1151,12 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
             const int sz = min(max((int)floor(fz * k), 0), k - 1);
             return (sz * k + sy) * k + sx;
         };
-        for (int j = cs + lane; j < ce; j += 64)
-            atomicMin(&rp[sub_of(j)], ((unsigned long long)link_key(j, rnd) << 32) | (unsigned)j);
+        int sj0 = 0;   // the sub-cell of this lane's first particle, kept for the hooks below
+        for (int j = cs + lane; j < ce; j += 64) {
+            const int sj = sub_of(j);
+            if (j < cs + 64) sj0 = sj;
+            atomicMin(&rp[sj], ((unsigned long long)link_key(j, rnd) << 32) | (unsigned)j);
+        }
         __builtin_amdgcn_wave_barrier();
         if (adj) {
             // the occupied sub-cells, listed (there are at most as many as
@@ -1219,7 +1223,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
             __builtin_amdgcn_wave_barrier();
         }
         for (int j = cs + lane; j < ce; j += 64) {
-            const int sj = sub_of(j);
+            const int sj = j < cs + 64 ? sj0 : sub_of(j);
             const int r = (int)(unsigned)(rp[adj ? lds_find(jf, sj) : sj] & 0xffffffffull);
             if (r != j) p.parent[j] = r;   // a key smaller than j's: a valid hook of a root
         }
