@@ -251,7 +251,10 @@ fof_status fof_get_stats(fof_ctx *ctx, fof_stats *out);
  * the graph holds kernel launches only. d_pos, d_group_index, d_group_size
  * and the workspace must stay allocated while the graph may be replayed.
  * fof_graph_launch replays it on the context's stream; the per-box group
- * counts stay on the device (fof_read_n_groups).
+ * counts stay on the device (fof_read_n_groups). Inside the graph the
+ * sub-cell pre-merge of dense cells runs beside the union pass of the
+ * per-particle search's links (the two touch disjoint sets of particles); a
+ * replay as a whole is still ordered on the context's stream.
  * A graph of several boxes reads the box table held in the workspace. Eager
  * calls on the same context may replace that table: a build of one box or of
  * another geometry, or fof_relink. fof_graph_launch then returns

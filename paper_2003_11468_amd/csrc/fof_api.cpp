@@ -793,12 +793,17 @@ fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return FOF_ERR_DEVICE;
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return FOF_ERR_DEVICE;
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    // a second captured stream, onto which the link phase forks the pre-merge
+    fof::Fork fk;
+    hipError_t e = hipStreamCreateWithFlags(&fk.side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fk.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fk.join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         // no per-kernel events inside a graph
         e = fof::launch_clear(ctx->dev, cs, nullptr);
         if (e == hipSuccess) e = fof::launch_build(ctx->dev, cs, nullptr);
-        if (e == hipSuccess) e = fof::launch_link(ctx->dev, cs, nullptr);
+        if (e == hipSuccess) e = fof::launch_link(ctx->dev, cs, nullptr, &fk);
         if (e == hipSuccess) e = fof::launch_finalize(ctx->dev, cs, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -817,6 +822,9 @@ fof_status fof_graph_capture(fof_ctx *ctx, const float *d_pos, const int64_t *h_
         }
     }
     (void)hipStreamDestroy(cs);
+    if (fk.side) (void)hipStreamDestroy(fk.side);
+    if (fk.fork) (void)hipEventDestroy(fk.fork);
+    if (fk.join) (void)hipEventDestroy(fk.join);
     ctx->state = 0;
     return dev_err(e);
 }

@@ -147,7 +147,14 @@ struct KernelTimer {
 // `t` may be null.
 hipError_t launch_clear(const Plan &p, hipStream_t stream, KernelTimer *t);
 hipError_t launch_build(const Plan &p, hipStream_t stream, KernelTimer *t);
-hipError_t launch_link(const Plan &p, hipStream_t stream, KernelTimer *t);
+// A second stream onto which the link phase may fork a kernel that is
+// independent of the others, with the events of the fork and of the join
+// (all null: every kernel on `stream`).
+struct Fork {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+hipError_t launch_link(const Plan &p, hipStream_t stream, KernelTimer *t, const Fork *fk = nullptr);
 // A fresh forest over the built cells (fof_kernels.hip): parent, sizes, group
 // minima and the per-run counters reset, cells and dense work items kept.
 hipError_t launch_relink_reset(const Plan &p, hipStream_t stream);

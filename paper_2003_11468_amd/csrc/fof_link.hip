@@ -1484,7 +1484,7 @@ __global__ void __launch_bounds__(kBlock) k_link_rest(Plan p)
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <bool kFP64, bool kStats>
-void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
+hipError_t launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t, const Fork *fk)
 {
     Plan first = p;
     first.sample = p.giant_skip;   // the giant-component skip starts from the axis links
@@ -1492,11 +1492,30 @@ void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
     hipLaunchKernelGGL((k_link_sparse<kFP64, kStats>), dim3((unsigned)p.sparse_blocks), dim3(kBlock), 0, stream,
                        first);
     if (t) t->mark(K_LINK_SPARSE, true, stream);
+    // the sub-cell pre-merge would merge across slab faces: not in domain mode
+    const bool premerge = p.domains <= 1 && p.premerge;
+    // The pre-merge reads and writes the parents of particles in dense cells
+    // only, the union pass those of particles in sparse cells only (the
+    // per-particle search pairs sparse cells with sparse cells): given a
+    // second stream the two run side by side, the pre-merge waiting for the
+    // cell sort alone, and the wavefront search waits for both. Not with
+    // per-kernel timers, whose events time each kernel alone.
+    const bool beside = premerge && fk && fk->side && !t;
+    if (beside) {
+        hipError_t e = hipEventRecord(fk->fork, stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(fk->side, fk->fork, 0);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_dense_premerge, dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, fk->side, p);
+        e = hipEventRecord(fk->join, fk->side);
+        if (e != hipSuccess) return e;
+    }
     if (t) t->mark(K_UNION_EDGES, false, stream);
     hipLaunchKernelGGL((k_union_edges<kStats>), dim3(kUnionParts * kEdgeSlices), dim3(kBlock), 0, stream, p);
     if (t) t->mark(K_UNION_EDGES, true, stream);
-    // the sub-cell pre-merge would merge across slab faces: not in domain mode
-    if (p.domains <= 1 && p.premerge) {
+    if (beside) {
+        const hipError_t e = hipStreamWaitEvent(stream, fk->join, 0);
+        if (e != hipSuccess) return e;
+    } else if (premerge) {
         if (t) t->mark(K_PREMERGE, false, stream);
         hipLaunchKernelGGL(k_dense_premerge, dim3((unsigned)p.dense_blocks), dim3(kBlock), 0, stream, p);
         if (t) t->mark(K_PREMERGE, true, stream);
@@ -1534,22 +1553,19 @@ void launch_link_t(const Plan &p, hipStream_t stream, KernelTimer *t)
         hipLaunchKernelGGL(k_gm_apply, dim3(g), dim3(kBlock), 0, stream, p);
         if (t) t->mark(K_UNION_EDGES, true, stream);
     }
+    return hipSuccess;
 }
 
 }  // namespace
 
-hipError_t launch_link(const Plan &p, hipStream_t stream, KernelTimer *t)
+hipError_t launch_link(const Plan &p, hipStream_t stream, KernelTimer *t, const Fork *fk)
 {
     if (p.n == 0) return hipSuccess;
     const bool fp64 = p.predicate == 0;
-    if (fp64) {
-        if (p.stats) launch_link_t<true, true>(p, stream, t);
-        else launch_link_t<true, false>(p, stream, t);
-    } else {
-        if (p.stats) launch_link_t<false, true>(p, stream, t);
-        else launch_link_t<false, false>(p, stream, t);
-    }
-    return hipGetLastError();
+    hipError_t e;
+    if (fp64) e = p.stats ? launch_link_t<true, true>(p, stream, t, fk) : launch_link_t<true, false>(p, stream, t, fk);
+    else e = p.stats ? launch_link_t<false, true>(p, stream, t, fk) : launch_link_t<false, false>(p, stream, t, fk);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 int64_t max_dense_items(int64_t n, int dense_min)

@@ -485,6 +485,38 @@ def test_graph_replays_match_eager():
         f.close()
 
 
+@pytest.mark.parametrize("predicate", PREDICATES)
+@pytest.mark.parametrize("premerge,stats", [(True, False), (False, False), (True, True)])
+def test_graph_with_dense_cells_matches_oracle(predicate, premerge, stats):
+    """A graph over boxes with many dense cells: the captured link phase runs
+    the sub-cell pre-merge on a second captured stream beside the union pass;
+    every replay (with eager work between) equals the oracle."""
+    w = synth.make("batched256", n_boxes=12, size_scale=0.05)
+    ref = oracle.fof_boxes(w.pos, w.offsets, w.box, w.lx)
+    f = fof.FoF(predicate, cell_factor=1.5, dense_min=8, stats=stats,
+                schedule=fof.schedule_bits(premerge=premerge))
+    try:
+        p = torch.from_numpy(w.pos).cuda()
+        label, size = f.outputs(w.n)
+        f.run(p, w.offsets, w.box, w.lx, label, size)
+        if stats:
+            assert f.stats()["dense_items"] > 0
+        f.capture(p, w.offsets, w.box, w.lx, label, size)
+        for rep in range(3):
+            label.fill_(-7)
+            size.fill_(-7)
+            f.replay()
+            ng = f.n_groups(w.n_boxes)
+            assert np.array_equal(label.cpu().numpy(), ref[0]), rep
+            assert np.array_equal(size.cpu().numpy(), ref[1]), rep
+            assert np.array_equal(ng, ref[2]), rep
+            lab2, _, _ = f.run(p[: w.offsets[2]].contiguous(), w.offsets[:3], w.box[:2], w.lx[:2])
+            assert np.array_equal(lab2.cpu().numpy(), ref[0][: w.offsets[2]])
+            f.run(p, w.offsets, w.box, w.lx, label, size)   # the captured geometry back in the workspace
+    finally:
+        f.close()
+
+
 def test_graph_refused_after_its_box_table_is_replaced():
     """A multi-box graph reads the box table in the workspace: after an eager
     build of another geometry (or of one box, or a relink) the host refuses to
