@@ -408,6 +408,26 @@ static_assert(kCntCap >= kOrderCap, "a segment placed through LDS is one window"
 // kWordsMax: the occupancy words of the largest segment this instance takes
 // (segments of up to 2^14 cells: one word per thread, the smaller LDS
 // footprint; above: several per thread).
+// Position of the t-th lowest set bit of m (t < popcount(m)), by halving the
+// window with population counts.
+__device__ __forceinline__ int nth_bit(unsigned m, int t)
+{
+    int pos = 0;
+#pragma unroll
+    for (int w = 16; w > 0; w >>= 1) {
+        const unsigned low = m & ((1u << w) - 1u);
+        const int c = __popc(low);
+        if (t >= c) {
+            t -= c;
+            m >>= w;
+            pos += w;
+        } else {
+            m = low;
+        }
+    }
+    return pos;
+}
+
 template <int kWordsMax>
 __global__ void __launch_bounds__(kSegBlock) __attribute__((amdgpu_waves_per_eu(kWordsMax <= 1024 ? 8 : 6))) k_cell_sort(Plan p)
 {
@@ -568,13 +588,18 @@ __global__ void __launch_bounds__(kSegBlock) __attribute__((amdgpu_waves_per_eu(
                             if (wbase[mid] <= rk) lo = mid;
                             else hi = mid - 1;
                         }
-                        unsigned m = bits[lo];
-                        for (int t = rk - wbase[lo]; t > 0; --t) m &= m - 1u;   // drop the lower occupied cells
-                        const int64_t gc = cell0 + (lo << 5) + (__ffs(m) - 1);
-                        const int bx = p.n_boxes == 1 ? 0 : find_box(p.box_p0, p.n_boxes, start);
-                        // the cell's coordinates in its box (nc <= 2^16 per axis)
-                        const int64_t nc = box_of(p, bx).nc, local = gc - box_of(p, bx).cell_base;
-                        const int cx = (int)(local % nc), cy = (int)((local / nc) % nc), cz = (int)(local / (nc * nc));
+                        const int64_t gc = cell0 + (lo << 5) + nth_bit(bits[lo], rk - wbase[lo]);
+                        // the segment's box, kept from step 1, unless the cell lies in another
+                        const int bx = p.n_boxes == 1 ? 0 : find_box_hint(p.box_p0, p.n_boxes, start, hint);
+                        // the cell's coordinates in its box: local < nc^3 <= 2^33 and the
+                        // divisors are below 2^22, so the double quotients truncate exactly
+                        const BoxDev &bd = box_of(p, bx);
+                        const int nc = bd.nc;
+                        const int64_t local = gc - bd.cell_base, nc2 = (int64_t)nc * nc;
+                        const int cz = (int)((double)local / (double)nc2);
+                        const int rem = (int)(local - cz * nc2);
+                        const int cy = (int)((double)rem / (double)nc);
+                        const int cx = rem - cy * nc;
                         for (int q = 0; q < v; q += 64, ++slot)
                             if (slot < p.max_items) p.items[slot] = make_int4(cx | (cy << 16), start + q, bx, cz);
                         // the cell's slots, in the masks by which the per-particle search skips dense tiles
