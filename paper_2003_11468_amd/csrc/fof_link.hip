@@ -130,14 +130,26 @@ __device__ __forceinline__ int lds_find(int *f, int x)
 // bit is the component's smallest member. No branch and no memory access.
 __device__ __forceinline__ unsigned long long close_rows(unsigned long long row, unsigned long long todo)
 {
-    while (todo) {
-        const int k = __ffsll((long long)todo) - 1;
-        todo &= todo - 1ull;
-        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)row, k);
-        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(row >> 32), k);
-        if ((row >> k) & 1ull) row |= ((unsigned long long)hi << 32) | lo;
+    // the two words of each row apart, so that the test of bit k reads one
+    // word (k below 32: the low one) and its sign-extended bit masks row k in
+    unsigned lo = (unsigned)row, hi = (unsigned)(row >> 32);
+    for (unsigned t = (unsigned)todo; t; t &= t - 1u) {
+        const int k = __ffs(t) - 1;
+        const unsigned klo = (unsigned)__builtin_amdgcn_readlane((int)lo, k);
+        const unsigned khi = (unsigned)__builtin_amdgcn_readlane((int)hi, k);
+        const unsigned m = (unsigned)__builtin_amdgcn_sbfe((int)lo, (unsigned)k, 1u);
+        lo |= klo & m;
+        hi |= khi & m;
     }
-    return row;
+    for (unsigned t = (unsigned)(todo >> 32); t; t &= t - 1u) {
+        const int k = __ffs(t) - 1;
+        const unsigned klo = (unsigned)__builtin_amdgcn_readlane((int)lo, k + 32);
+        const unsigned khi = (unsigned)__builtin_amdgcn_readlane((int)hi, k + 32);
+        const unsigned m = (unsigned)__builtin_amdgcn_sbfe((int)hi, (unsigned)k, 1u);
+        lo |= klo & m;
+        hi |= khi & m;
+    }
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ __forceinline__ void lds_unite(int *f, int a, int b)
