@@ -875,7 +875,8 @@ __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, co
                                             int &known1, unsigned long long &links, unsigned long long &band,
                                             unsigned &retries)
 {
-    auto fresh = [&](int rj) { return kStats || (rj != root_i && rj != known0); };
+    // non-short-circuit forms: the compares run flat, with no branch around them
+    auto fresh = [&](int rj) { return kStats || ((rj != root_i) & (rj != known0)); };
     int kk = 0;
     if constexpr (!kFP64) {
         const int G4 = 4 * G;
@@ -886,15 +887,15 @@ __device__ __forceinline__ void dense_batch(const Plan &p, const BoxRegs &br, co
             const float r1 = dist2_f32(q1, hx, hy, hz);
             const float r2 = dist2_f32(q2, hx, hy, hz);
             const float r3 = dist2_f32(q3, hx, hy, hz);
-            bool c0 = r0 <= br.hi32 && fresh(__float_as_int(q0.w));
-            bool c1 = r1 <= br.hi32 && fresh(__float_as_int(q1.w));
-            bool c2 = r2 <= br.hi32 && fresh(__float_as_int(q2.w));
-            bool c3 = r3 <= br.hi32 && fresh(__float_as_int(q3.w));
+            bool c0 = (r0 <= br.hi32) & fresh(__float_as_int(q0.w));
+            bool c1 = (r1 <= br.hi32) & fresh(__float_as_int(q1.w));
+            bool c2 = (r2 <= br.hi32) & fresh(__float_as_int(q2.w));
+            bool c3 = (r3 <= br.hi32) & fresh(__float_as_int(q3.w));
             if constexpr (kSelf) {
-                c0 = c0 && st.slot[k0] > i;
-                c1 = c1 && st.slot[k1] > i;
-                c2 = c2 && st.slot[k2] > i;
-                c3 = c3 && st.slot[k3] > i;
+                c0 = c0 & (st.slot[k0] > i);
+                c1 = c1 & (st.slot[k1] > i);
+                c2 = c2 & (st.slot[k2] > i);
+                c3 = c3 & (st.slot[k3] > i);
             }
             if (__ballot(c0 || c1 || c2 || c3)) {
                 dense_hit<kFP64, kStats, kGeneral>(p, br, st, k0, c0, r0, pi, root_i, known0, known1, links, band,
