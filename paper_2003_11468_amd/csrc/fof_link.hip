@@ -389,9 +389,10 @@ __device__ __forceinline__ void sparse_pairs(const Plan &p, SparseLds &L, EdgeSi
                         dz = axis_diff(hp.z, c.z, (code >> 4) & 3, bx.L32);
                     }
                     const float rr = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    if (rr < bx.lo32) link = true;
-                    else if (rr > bx.hi32) link = false;
-                    else {
+                    link = rr < bx.lo32;
+                    // the guard band (rare), decided in double; one branch, the
+                    // compares flat (a NaN lands in the band and fails there)
+                    if (!(rr < bx.lo32) & !(rr > bx.hi32)) {
                         if (kStats) ++band;
                         link = link_fp64(hp.x, hp.y, hp.z, c.x, c.y, c.z, bx.L, bx.half, bx.l2, strict);
                     }
