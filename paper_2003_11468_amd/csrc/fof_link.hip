@@ -1121,6 +1121,17 @@ __global__ void __launch_bounds__(kBlock) k_link_dense(Plan p)
 // stores.
 constexpr int kMaxSub = 512;
 
+// Coordinates of sub-cell t on a k^3 grid (t < k^3 <= kMaxSub): the float
+// quotients of t + 1/2 lie at least 1/(2 k^2) from an integer, far above
+// their rounding error, so truncation gives the integer quotients.
+__device__ __forceinline__ void sub_xyz(int t, int k, float inv_k, float inv_k2, int &sx, int &sy, int &sz)
+{
+    sz = (int)(((float)t + 0.5f) * inv_k2);
+    const int r = t - sz * k * k;
+    sy = (int)(((float)r + 0.5f) * inv_k);
+    sx = r - sy * k;
+}
+
 __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
 {
     // per sub-cell: (hooking key << 32 | particle) of its first particle, ~0 when empty
@@ -1149,6 +1160,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
         const int k = bd.sub_k;
         if (k == 0) continue;
         const bool adj = bd.sub_adj != 0;
+        const float inv_k = 1.0f / (float)k, inv_k2 = 1.0f / (float)(k * k);
         const int ce = __builtin_amdgcn_readfirstlane(sp.y);
         const int nsub = k * k * k;
         for (int t = lane; t < nsub; t += 64) {
@@ -1197,7 +1209,8 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
                 int t = 0;
                 if (lane < n_used) {
                     t = ul[lane];
-                    const int sx = t % k, sy = (t / k) % k, sz = t / (k * k);
+                    int sx, sy, sz;
+                    sub_xyz(t, k, inv_k, inv_k2, sx, sy, sz);
                     row = 1ull << lane;
 #pragma unroll
                     for (int o = 0; o < 27; ++o) {   // no branch: an outside neighbour reads sub-cell t
@@ -1218,7 +1231,8 @@ __global__ void __launch_bounds__(kBlock) k_dense_premerge(Plan p)
             } else {
                 for (int q = lane; q < n_used; q += 64) {
                     const int t = ul[q];
-                    const int sx = t % k, sy = (t / k) % k, sz = t / (k * k);
+                    int sx, sy, sz;
+                    sub_xyz(t, k, inv_k, inv_k2, sx, sy, sz);
                     for (int o = 14; o < 27; ++o) {
                         const int ux = sx + o % 3 - 1, uy = sy + (o / 3) % 3 - 1, uz = sz + o / 9 - 1;
                         if (ux < 0 || ux >= k || uy < 0 || uy >= k || uz >= k) continue;
