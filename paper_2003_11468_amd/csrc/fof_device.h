@@ -197,21 +197,20 @@ __device__ __forceinline__ void find_many(int *parent, int (&x)[kN], bool (&done
 #pragma unroll
         for (int v = 0; v < kN; ++v) px[v] = ld_rel(parent + x[v]);
 #pragma unroll
-        for (int v = 0; v < kN; ++v) done[v] = done[v] || px[v] == x[v];
+        for (int v = 0; v < kN; ++v) done[v] = done[v] | (px[v] == x[v]);
 #pragma unroll
         for (int v = 0; v < kN; ++v) gx[v] = ld_rel(parent + px[v]);
+        // a node still searching moves to its grandparent (its parent when
+        // that is the root, which is then equal) and, below the root, halves
+        // the path; only the store is conditional, the rest has no branch
         bool any = false;
 #pragma unroll
         for (int v = 0; v < kN; ++v) {
-            if (done[v]) continue;
-            if (gx[v] == px[v]) {
-                x[v] = px[v];
-                done[v] = true;
-            } else {
-                st_rel(parent + x[v], gx[v]);
-                x[v] = gx[v];
-                any = true;
-            }
+            const bool halve = !done[v] & (gx[v] != px[v]);
+            if (halve) st_rel(parent + x[v], gx[v]);
+            x[v] = done[v] ? x[v] : gx[v];
+            done[v] = done[v] | (gx[v] == px[v]);
+            any = any | halve;
         }
         if (!any) return;
     }
