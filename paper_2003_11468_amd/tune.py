@@ -39,7 +39,7 @@ import numpy as np
 
 from . import FoF, FoFError, fof_build_cells, fof_finalize, fof_link, schedule_bits
 
-CELL_FACTORS = (0.0, 1.25, 1.5, 2.0, 2.5, 3.0, 4.0)
+CELL_FACTORS = (0.0, 1.25, 1.375, 1.5, 2.0, 2.5, 3.0, 4.0)
 DENSE_MINS = (8, 16, 32)
 # one axis at a time, after the grid above; the first value is the default
 AXES = {

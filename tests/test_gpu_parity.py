@@ -136,7 +136,7 @@ def test_clustered_linking_lengths(predicate, b):
     assert_single(pos, lx, predicate=predicate)
 
 
-@pytest.mark.parametrize("cell_factor", [1.0, 1.5, 2.0, 3.0, 7.0])
+@pytest.mark.parametrize("cell_factor", [1.0, 1.375, 1.5, 2.0, 3.0, 7.0])
 def test_cell_sizes(cell_factor):
     n = 150000
     pos = synth.clustered(n, 5, 0, 0.6)
